@@ -1,0 +1,416 @@
+"""Seeded synthetic workloads: mechanisms, cell states and the served request trace.
+
+The paper's mechanisms (hydrogen, H2/CO, GRI-Mech 3.0, USC Mech II) and its
+ignition-sampled initial conditions (Sec. 3, "Results and discussion") are not
+available, so every workload here is synthetic, seeded and reproducible.  The
+sizes match the paper's four mechanisms: 9/38, 13/54, 53/634 and 111/1566
+species/irreversible reactions.  Like the paper's converted mechanisms
+(Appendix A turns each reversible reaction into two irreversible ones), the
+reactions come as forward/reverse pairs, each direction with its own Arrhenius
+parameters.
+
+This module only draws inputs.  It evaluates no right-hand side and integrates
+nothing; the one rate-like quantity it computes is a log-space upper bound of a
+reaction's pseudo-first-order rate, used to reject parameter draws that would
+make the system stiffer than a stated stage budget allows.
+
+Units carried by every mechanism dict:
+  W           g/mol
+  A           (cm^3/mol)^(m-1) / s, m = number of reactant molecules
+  beta        dimensionless temperature exponent
+  Ea          J/mol
+  nasa_low/high  NASA 7-coefficient polynomials, Cp/R and H/(R T) forms
+  T_mid       K, switch between the low and high fit ranges
+  reac, prod  [n_R][3] species indices with repetition (a species listed twice
+              has stoichiometric coefficient 2); -1 marks an empty slot
+States: T in K, P in Pa, Y mass fractions (rows sum to 1).
+"""
+from __future__ import annotations
+
+import functools
+import math
+
+import numpy as np
+
+R_J = 8.31446261815324          # J/(mol K)
+R_ERG = 8.31446261815324e7      # erg/(mol K)
+ATM = 101325.0                  # Pa
+
+ATOMIC_WEIGHTS = {"H": 1.008, "C": 12.011, "N": 14.007, "O": 15.999, "Ar": 39.948}
+
+# Reactant / product molecularity distribution (1, 2 or 3 molecules per side).
+_SIDE_SIZE_P = np.array([0.25, 0.60, 0.15])
+
+
+def _compositions(elements, limits, max_atoms):
+    """All nonzero element-count vectors over `elements` (Ar excluded) within limits."""
+    mol_elems = [e for e in elements if e != "Ar"]
+    ranges = [range(limits[e] + 1) for e in mol_elems]
+    out = []
+    for counts in np.ndindex(*[len(r) for r in ranges]):
+        tot = sum(counts)
+        if 0 < tot <= max_atoms:
+            vec = [0] * len(elements)
+            for e, c in zip(mol_elems, counts):
+                vec[elements.index(e)] = c
+            out.append(tuple(vec))
+    return out
+
+
+def _nasa_species(rng, inert=False):
+    """Random two-range NASA-7 polynomials.
+
+    Molar Cp stays within 20-60 J/(mol K) on 300-3500 K.  The low range equals
+    the high range plus c (T - T_mid)^2, so Cp and dCp/dT are continuous at
+    T_mid; a6 of the high range is fitted so H is continuous there too.
+    Returns (low[7], high[7], T_mid, dHf_J).
+    """
+    T_mid = 1000.0
+    if inert:
+        hi = np.array([2.5, 0, 0, 0, 0, 0.0, 0.0])
+        lo = hi.copy()
+        hf = 0.0
+        # H(298.15) = 0 for the inert monatomic species
+        lo[5] = -2.5 * 298.15
+        hi[5] = lo[5]
+        return lo, hi, T_mid, hf
+    Tg = np.linspace(300.0, 3500.0, 161)
+    while True:
+        base = rng.uniform(2.5, 4.0)
+        d = rng.uniform(0.5, 2.0)
+        e5 = rng.uniform(-0.01, 0.01) * d
+        hi = np.zeros(7)
+        hi[0] = base
+        hi[1] = 1.2 * d / 1e3
+        hi[2] = -0.5 * d / 1e6
+        hi[3] = 0.08 * d / 1e9
+        hi[4] = e5 / 1e12
+        c = rng.uniform(-1.0, 1.0) * 1e-7
+        lo = hi.copy()
+        lo[0] += c * T_mid * T_mid
+        lo[1] += -2.0 * c * T_mid
+        lo[2] += c
+        cp_hi = np.polyval(hi[4::-1], Tg)
+        cp_lo = np.polyval(lo[4::-1], Tg)
+        cp = np.where(Tg >= T_mid, cp_hi, cp_lo) * R_J
+        if cp.min() >= 20.0 and cp.max() <= 60.0:
+            break
+    hf = rng.uniform(-1.5e5, 1.5e5)
+
+    def hint(a, T):  # integral of Cp/R dT without the constant
+        return a[0] * T + a[1] * T**2 / 2 + a[2] * T**3 / 3 + a[3] * T**4 / 4 + a[4] * T**5 / 5
+
+    lo[5] = hf / R_J - hint(lo, 298.15)
+    hi[5] = lo[5] + hint(lo, T_mid) - hint(hi, T_mid)
+    return lo, hi, T_mid, hf
+
+
+def _ln_rate_bound(lnA, beta, Ea, m, T, P_pa):
+    """ln of m * k(T) * C_tot(T)^(m-1), the pseudo-first-order rate bound."""
+    ln_ctot = math.log(P_pa * 10.0) - math.log(R_ERG) - np.log(T)
+    return math.log(m) + lnA + beta * np.log(T) - Ea / (R_J * T) + (m - 1) * ln_ctot
+
+
+def make_mechanism(n_species, n_reactions, elements, seed, *, ea_max=2e5,
+                   T_lo=800.0, T_hi=2200.0, P_max=ATM, dt=1e-6, s_target=30,
+                   limits=None, max_atoms=6, name=None):
+    """Seeded, element-balanced mechanism of forward/reverse reaction pairs.
+
+    Arrhenius draws: log10 A ~ U(6, 14), beta ~ U(-2, 2), Ea ~ U(0, ea_max).
+    A draw is rejected (and redrawn) while its rate bound on [T_lo, T_hi] at
+    P_max exceeds lambda_cap = ((s_target-1)^2 - 1) / (1.54 dt), the spectral
+    radius whose RKC stage count over one full step dt is s_target.
+    """
+    assert n_reactions % 2 == 0, "reactions come as forward/reverse pairs"
+    rng = np.random.Generator(np.random.PCG64(seed))
+    if limits is None:
+        limits = {"C": 2, "H": 4, "O": 2, "N": 2}
+    has_ar = "Ar" in elements
+    comps = _compositions(elements, limits, max_atoms)
+    n_mol = n_species - (1 if has_ar else 0)
+    if len(comps) < n_mol:
+        raise ValueError("not enough distinct compositions for %d species" % n_species)
+    # prefer small molecules: weight 1/atoms^1.5
+    w = np.array([1.0 / (sum(c) ** 1.5) for c in comps])
+    w /= w.sum()
+    mol_elems = [e for e in elements if e != "Ar"]
+    for _ in range(1000):
+        pick = rng.choice(len(comps), size=n_mol, replace=False, p=w)
+        chosen = [comps[i] for i in pick]
+        present = np.array(chosen).sum(axis=0)
+        if all(present[elements.index(e)] > 0 for e in mol_elems):
+            break
+    else:
+        raise RuntimeError("could not cover every element")
+    if has_ar:
+        ar = [0] * len(elements)
+        ar[elements.index("Ar")] = 1
+        chosen.append(tuple(ar))
+    comp = np.array(chosen, dtype=np.int64)
+    W = comp @ np.array([ATOMIC_WEIGHTS[e] for e in elements])
+
+    nasa_low = np.zeros((n_species, 7))
+    nasa_high = np.zeros((n_species, 7))
+    T_mid = np.zeros(n_species)
+    hf = np.zeros(n_species)
+    for i in range(n_species):
+        inert = has_ar and i == n_species - 1
+        lo, hi, tm, h = _nasa_species(rng, inert=inert)
+        nasa_low[i], nasa_high[i], T_mid[i], hf[i] = lo, hi, tm, h
+
+    # index of multisets (sorted species tuples) of size 1..3 by composition
+    index = {1: {}, 2: {}, 3: {}}
+    for size in (1, 2, 3):
+        for ms in _multisets(n_species, size):
+            key = tuple(comp[list(ms)].sum(axis=0))
+            index[size].setdefault(key, []).append(ms)
+
+    n_pairs = n_reactions // 2
+    pairs = set()
+    reac = np.full((n_reactions, 3), -1, dtype=np.int32)
+    prod = np.full((n_reactions, 3), -1, dtype=np.int32)
+    guard = 0
+    p = 0
+    while p < n_pairs:
+        guard += 1
+        if guard > 200000:
+            raise RuntimeError("could not draw enough distinct balanced reactions")
+        m = 1 + rng.choice(3, p=_SIDE_SIZE_P)
+        q = 1 + rng.choice(3, p=_SIDE_SIZE_P)
+        r_ms = tuple(sorted(rng.choice(n_species, size=m, replace=True).tolist()))
+        key = tuple(comp[list(r_ms)].sum(axis=0))
+        cands = [c for c in index[q].get(key, []) if c != r_ms]
+        if not cands:
+            continue
+        p_ms = cands[rng.integers(len(cands))]
+        pk = (min(r_ms, p_ms), max(r_ms, p_ms))
+        if pk in pairs:
+            continue
+        pairs.add(pk)
+        reac[2 * p, :m] = r_ms
+        prod[2 * p, :q] = p_ms
+        reac[2 * p + 1, :q] = p_ms
+        prod[2 * p + 1, :m] = r_ms
+        p += 1
+
+    lam_cap = ((s_target - 1) ** 2 - 1) / (1.54 * dt)
+    ln_cap = math.log(lam_cap)
+    Tg = np.linspace(T_lo, T_hi, 33)
+    A = np.zeros(n_reactions)
+    beta = np.zeros(n_reactions)
+    Ea = np.zeros(n_reactions)
+    msize = (reac >= 0).sum(axis=1)
+    for j in range(n_reactions):
+        for _ in range(100000):
+            lA = rng.uniform(6.0, 14.0) * math.log(10.0)
+            b = rng.uniform(-2.0, 2.0)
+            e = rng.uniform(0.0, ea_max)
+            if _ln_rate_bound(lA, b, e, msize[j], Tg, P_max).max() <= ln_cap:
+                break
+        else:
+            raise RuntimeError("stiffness cap unreachable")
+        A[j], beta[j], Ea[j] = math.exp(lA), b, e
+    # keep at least 10 % of reactions active (rate >= 1e-3/dt at T_hi)
+    ln_act = math.log(1e-3 / dt)
+
+    def active(j):
+        return _ln_rate_bound(math.log(A[j]), beta[j], Ea[j], msize[j],
+                              np.array([T_hi]), P_max)[0] >= ln_act
+
+    act = np.array([active(j) for j in range(n_reactions)])
+    tries = 0
+    while act.mean() < 0.10 and tries < 100 * n_reactions:
+        j = int(rng.choice(np.flatnonzero(~act)))
+        lA = rng.uniform(6.0, 14.0) * math.log(10.0)
+        b = rng.uniform(-2.0, 2.0)
+        e = rng.uniform(0.0, ea_max)
+        tries += 1
+        if _ln_rate_bound(lA, b, e, msize[j], Tg, P_max).max() <= ln_cap:
+            A[j], beta[j], Ea[j] = math.exp(lA), b, e
+            act[j] = active(j)
+
+    names = []
+    for i in range(n_species):
+        s = "".join("%s%s" % (el, "" if c == 1 else c)
+                    for el, c in zip(elements, comp[i]) if c > 0)
+        names.append(s)
+    return {
+        "name": name or "synth_%dsp_%drx_seed%d" % (n_species, n_reactions, seed),
+        "seed": seed,
+        "n_species": n_species,
+        "n_reactions": n_reactions,
+        "elements": list(elements),
+        "species": names,
+        "comp": comp,
+        "W": W,
+        "nasa_low": nasa_low,
+        "nasa_high": nasa_high,
+        "T_mid": T_mid,
+        "dHf": hf,
+        "reac": reac,
+        "prod": prod,
+        "A": A,
+        "beta": beta,
+        "Ea": Ea,
+        "lambda_cap": lam_cap,
+        "active_fraction": float(act.mean()),
+    }
+
+
+def _multisets(n, size):
+    if size == 1:
+        for a in range(n):
+            yield (a,)
+    elif size == 2:
+        for a in range(n):
+            for b in range(a, n):
+                yield (a, b)
+    else:
+        for a in range(n):
+            for b in range(a, n):
+                for c in range(b, n):
+                    yield (a, b, c)
+
+
+def make_states(mech, n_cells, seed, *, T_dist, P_dist, Y_dist, order="shuffled"):
+    """Seeded cell states.
+
+    T_dist: ("uniform", lo, hi) | ("bimodal", m1, m2, sd)
+    P_dist: ("const", P_pa) | ("uniform", lo_pa, hi_pa)
+    Y_dist: ("dirichlet",) | ("majors", n_major, m_lo, m_hi)
+    order:  "shuffled" (cells in random order, the paper's worst case) or
+            "sorted" (by temperature, the paper's similar-neighbour case)
+    Returns dict T[n], P[n], Y[n][n_S] (float64, C-contiguous).
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    nS = mech["n_species"]
+    if T_dist[0] == "uniform":
+        T = rng.uniform(T_dist[1], T_dist[2], size=n_cells)
+    elif T_dist[0] == "bimodal":
+        hot = rng.random(n_cells) < 0.5
+        T = np.where(hot, rng.normal(T_dist[2], T_dist[3], n_cells),
+                     rng.normal(T_dist[1], T_dist[3], n_cells))
+    else:
+        raise ValueError(T_dist)
+    if P_dist[0] == "const":
+        P = np.full(n_cells, float(P_dist[1]))
+    else:
+        P = rng.uniform(P_dist[1], P_dist[2], size=n_cells)
+    if Y_dist[0] == "dirichlet":
+        Y = rng.dirichlet(np.ones(nS), size=n_cells)
+    elif Y_dist[0] == "majors":
+        nm = Y_dist[1]
+        majors = np.asarray(mech.get("major_species", list(range(nm))))
+        minors = np.setdiff1d(np.arange(nS), majors)
+        m = rng.uniform(Y_dist[2], Y_dist[3], size=n_cells)
+        Y = np.zeros((n_cells, nS))
+        Y[:, majors] = m[:, None] * rng.dirichlet(np.ones(nm), size=n_cells)
+        Y[:, minors] = (1.0 - m)[:, None] * rng.dirichlet(np.ones(len(minors)), size=n_cells)
+    else:
+        raise ValueError(Y_dist)
+    Y = Y / Y.sum(axis=1, keepdims=True)
+    if order == "sorted":
+        perm = np.argsort(T, kind="stable")
+        T, P, Y = T[perm], P[perm], Y[perm]
+    return {"T": np.ascontiguousarray(T, dtype=np.float64),
+            "P": np.ascontiguousarray(P, dtype=np.float64),
+            "Y": np.ascontiguousarray(Y, dtype=np.float64)}
+
+
+# Workload configurations (mechanism seed 1000+k, state seed 2000+k).
+CONFIGS = {
+    "c1": dict(n_species=9, n_reactions=38, elements=["H", "O", "N"], mech_seed=1001,
+               state_seed=2001, n_cells=1024, T=("uniform", 1000.0, 1500.0),
+               P=("const", ATM), Y=("dirichlet",), dt=1e-6, rtol=1e-6, atol=1e-10,
+               ea_max=2e5, T_range=(950.0, 1600.0), P_max=ATM, s_target=30,
+               label="9sp/38rx, 1024 cells, dt 1e-6"),
+    "c2": dict(n_species=13, n_reactions=54, elements=["H", "O", "C", "N"], mech_seed=1002,
+               state_seed=2002, n_cells=262144, T=("uniform", 900.0, 1800.0),
+               P=("uniform", ATM, 10 * ATM), Y=("dirichlet",), dt=1e-6, rtol=1e-6,
+               atol=1e-10, ea_max=2e5, T_range=(850.0, 1900.0), P_max=10 * ATM,
+               s_target=30, label="13sp/54rx, 262144 cells, dt 1e-6"),
+    "c3": dict(n_species=53, n_reactions=634, elements=["H", "O", "C", "N", "Ar"],
+               mech_seed=1003, state_seed=2003, n_cells=131072,
+               T=("uniform", 800.0, 2200.0), P=("const", ATM), Y=("majors", 5, 0.90, 0.99),
+               dt=1e-6, rtol=1e-6, atol=1e-10, ea_max=2e5, T_range=(750.0, 2300.0),
+               P_max=ATM, s_target=30, label="53sp/634rx, 131072 cells, dt 1e-6"),
+    "c4": dict(n_species=111, n_reactions=1566, elements=["H", "O", "C", "N", "Ar"],
+               mech_seed=1004, state_seed=2004, n_cells=65536,
+               T=("bimodal", 800.0, 2400.0, 20.0), P=("const", ATM), Y=("dirichlet",),
+               dt=1e-5, rtol=1e-6, atol=1e-10, ea_max=3e5, T_range=(700.0, 2500.0),
+               P_max=ATM, s_target=200, limits={"C": 3, "H": 8, "O": 3, "N": 2},
+               max_atoms=8, label="111sp/1566rx, 65536 cells, dt 1e-5"),
+}
+
+
+@functools.lru_cache(maxsize=None)
+def _cached_mech(name):
+    c = CONFIGS[name]
+    kw = {}
+    if "limits" in c:
+        kw["limits"] = c["limits"]
+        kw["max_atoms"] = c["max_atoms"]
+    m = make_mechanism(c["n_species"], c["n_reactions"], c["elements"], c["mech_seed"],
+                       ea_max=c["ea_max"], T_lo=c["T_range"][0], T_hi=c["T_range"][1],
+                       P_max=c["P_max"], dt=c["dt"], s_target=c["s_target"],
+                       name=name, **kw)
+    if c["Y"][0] == "majors":
+        rng = np.random.Generator(np.random.PCG64(c["mech_seed"] + 7))
+        m["major_species"] = sorted(rng.choice(c["n_species"] - 1, size=c["Y"][1],
+                                               replace=False).tolist())
+    return m
+
+
+def config_mechanism(name):
+    """The seeded mechanism of a named configuration (c1..c4)."""
+    return _cached_mech(name)
+
+
+def config_states(name, n_cells=None, order="shuffled", seed=None):
+    """Seeded states of a configuration; n_cells defaults to its full size."""
+    c = CONFIGS[name]
+    n = c["n_cells"] if n_cells is None else n_cells
+    return make_states(config_mechanism(name), n, c["state_seed"] if seed is None else seed,
+                       T_dist=c["T"], P_dist=c["P"], Y_dist=c["Y"], order=order)
+
+
+# ---- served workload: Poisson request trace --------------------------------
+
+C5_SEED = 3005
+
+
+@functools.lru_cache(maxsize=None)
+def c5_mechanism(kind, i):
+    """kind 13 or 53; i in 0..3: the served workload's mechanism sets."""
+    base = "c2" if kind == 13 else "c3"
+    c = CONFIGS[base]
+    m = make_mechanism(c["n_species"], c["n_reactions"], c["elements"], 3100 + 100 * (kind == 53) + i,
+                       ea_max=c["ea_max"], T_lo=c["T_range"][0], T_hi=c["T_range"][1],
+                       P_max=c["P_max"], dt=c["dt"], s_target=c["s_target"],
+                       name="c5_%dsp_%d" % (kind, i))
+    if c["Y"][0] == "majors":
+        m["major_species"] = list(range(c["Y"][1]))
+    return m
+
+
+def c5_trace(n_requests=2000, rate=200.0, seed=C5_SEED, log2_lo=10.0, log2_hi=16.0):
+    """Request list: arrival time (s), mechanism (kind, i), n_cells, dt, state seed."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    gaps = rng.exponential(1.0 / rate, size=n_requests)
+    t = np.cumsum(gaps)
+    out = []
+    for r in range(n_requests):
+        kind = 13 if rng.random() < 0.5 else 53
+        i = int(rng.integers(4))
+        n = int(round(2.0 ** rng.uniform(log2_lo, log2_hi)))
+        dt = 1e-6 if rng.random() < 0.5 else 1e-5
+        out.append({"id": r, "t_arrival": float(t[r]), "mech": (kind, i), "n_cells": n,
+                    "dt": dt, "state_seed": int(rng.integers(1 << 31))})
+    return out
+
+
+def c5_states(req):
+    base = "c2" if req["mech"][0] == 13 else "c3"
+    c = CONFIGS[base]
+    return make_states(c5_mechanism(*req["mech"]), req["n_cells"], req["state_seed"],
+                       T_dist=c["T"], P_dist=c["P"], Y_dist=c["Y"])
