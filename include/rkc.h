@@ -1,0 +1,181 @@
+/*
+ * rkc.h - C ABI of the MI355X (gfx950) batched chemical-kinetics integrator.
+ *
+ * Each grid cell of an operator-split reactive-flow simulation carries an
+ * independent constant-pressure adiabatic kinetics ODE for y = {T, Y_1..Y_nS}
+ * (Niemeyer & Sung, Sec. 2.2, Eqs. E:mass, E:spec-rate, E:rxn-rate,
+ * E:rxn-const, E:energy).  rkc_integrate advances every cell over one global
+ * chemistry step [0, dt] with internal sub-stepping (Sec. 3: the integrator
+ * takes initial conditions and a global time step and restarts every call)
+ * using either
+ *   - RKC: the second-order Runge-Kutta-Chebyshev method with adaptive step
+ *     size, stage count from a nonlinear power-method spectral radius
+ *     (Sec. 2.4), or
+ *   - RKCK: the fifth-order Runge-Kutta-Cash-Karp method with embedded error
+ *     estimate (Sec. 2.3, Table 1).
+ * All arithmetic is IEEE double precision in HIP kernels on the GPU.
+ *
+ * Conventions for every function:
+ *   - return value: RKC_OK (0) or a negative RKC_E* code; nothing is thrown
+ *     across the ABI; rkc_strerror() names a code.
+ *   - arrays are caller-owned.  By default they are host pointers, copied to
+ *     and from the device inside the call (which then returns after the work
+ *     completed).  With opts->device_ptrs != 0 every array argument (T, P, Y,
+ *     f, cell_status, opts->cell_counters) is a device pointer on the
+ *     mechanism's device; the work is enqueued on opts->stream and the call
+ *     returns without waiting unless a rkc_stats pointer is passed (then it
+ *     synchronises the stream to fill it).
+ *   - units: T in K, P in Pa, Y mass fractions, dt in s; mechanism units are
+ *     listed at rkc_mech_desc.
+ *   - calls that share one rkc_mech handle must not overlap in time (they share
+ *     the handle's device scratch: work-queue counter and statistics).
+ */
+#ifndef RKC_H
+#define RKC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ------------------------------------------------------ */
+#define RKC_OK        0
+#define RKC_EINVAL   (-1)   /* bad argument (NULL array, dt <= 0, rtol <= 0, size mismatch) */
+#define RKC_ENOMEM   (-2)   /* device or host allocation failed */
+#define RKC_EDEVICE  (-3)   /* a HIP runtime call failed */
+#define RKC_ECELLS   (-4)   /* call completed but at least one cell failed */
+#define RKC_ENOTSUP  (-5)   /* mechanism or option outside the compiled variants */
+
+/* ---- per-cell status (cell_status[i], counters column 6) --------------- */
+#define RKC_CELL_OK         0
+#define RKC_CELL_UNDERFLOW  1   /* proposed step fell below 10 u dt */
+#define RKC_CELL_MAXSTEPS   2   /* accepted + rejected steps reached max_steps */
+#define RKC_CELL_NONFINITE  3   /* f(y0), the spectral radius or the initial error was not finite */
+#define RKC_CELL_BADINPUT   4   /* T <= 0, P <= 0 or a non-finite input; cell left unchanged */
+
+/* ---- integration method ------------------------------------------------- */
+#define RKC_METHOD_RKC   0      /* Sec. 2.4 */
+#define RKC_METHOD_RKCK  1      /* Sec. 2.3, Table 1 */
+
+/* ---- launch schedule (never changes results: see rkc_integrate) --------- */
+#define RKC_SCHED_AUTO        0
+#define RKC_SCHED_PLAIN       1  /* one lane group per cell, grid covers all cells */
+#define RKC_SCHED_PERSISTENT  2  /* resident grid; groups pull cells from a device queue */
+
+/* Number of int32 per cell in opts->cell_counters. */
+#define RKC_NCOUNTERS 8
+/* Column order of opts->cell_counters rows. */
+enum { RKC_CNT_RHS = 0, RKC_CNT_STEPS = 1, RKC_CNT_REJECT = 2, RKC_CNT_SIGMA = 3,
+       RKC_CNT_SMAX = 4, RKC_CNT_SHASH = 5, RKC_CNT_STATUS = 6, RKC_CNT_POWER_ITER = 7 };
+
+typedef struct rkc_mech rkc_mech;   /* opaque, owned by the library */
+
+/* Mechanism description: irreversible reactions with Arrhenius rates
+ * (E:rxn-const), mass-action rates of progress (E:rxn-rate) and two-range
+ * NASA 7-coefficient thermodynamics (E:energy).  All arrays are host memory,
+ * read during rkc_mech_create only.
+ *   W          [n_species]            molar mass, g/mol (> 0)
+ *   nasa_low   [n_species][7]         Cp/R = a1 + a2 T + a3 T^2 + a4 T^3 + a5 T^4,
+ *   nasa_high  [n_species][7]         H/(R T) = a1 + a2 T/2 + ... + a5 T^4/5 + a6/T
+ *   T_mid      [n_species]            K; the high range is used iff T >= T_mid
+ *   reac, prod [n_reactions][3]       species indices with repetition (a species
+ *                                     listed twice has coefficient 2); -1 = empty;
+ *                                     at most 3 molecules per side
+ *   A          [n_reactions]          (cm^3/mol)^(m-1)/s, m = reactant molecules
+ *   beta       [n_reactions]          temperature exponent
+ *   Ea         [n_reactions]          J/mol
+ * A reaction immediately followed by its exact reverse is evaluated as one
+ * forward/reverse pair (net rate of progress), which is how mechanisms
+ * converted by the paper's Appendix A procedure are laid out. */
+typedef struct {
+    int32_t n_species, n_reactions;
+    const double *W;
+    const double *nasa_low;
+    const double *nasa_high;
+    const double *T_mid;
+    const int32_t *reac;
+    const int32_t *prod;
+    const double *A, *beta, *Ea;
+} rkc_mech_desc;
+
+/* Options; rkc_opts_default() fills the defaults shown. */
+typedef struct {
+    int32_t method;          /* RKC_METHOD_RKC */
+    int32_t s_max;           /* 1000: largest RKC stage count (>= 2) */
+    int32_t max_steps;       /* 1000000: accepted + rejected steps per cell */
+    int32_t lanes_per_cell;  /* 0 = automatic; else 8, 16, 32 or 64 */
+    int32_t schedule;        /* RKC_SCHED_AUTO */
+    int32_t block_groups;    /* lane groups per workgroup, 0 = automatic */
+    int32_t grid_blocks;     /* persistent grid size in workgroups, 0 = automatic */
+    int32_t device_ptrs;     /* 0: host arrays; 1: device arrays (see top) */
+    void   *stream;          /* hipStream_t; NULL = the null stream */
+    int32_t *cell_counters;  /* optional [n_cells][RKC_NCOUNTERS] per-cell counters */
+} rkc_opts;
+
+/* Aggregate statistics of one call. */
+typedef struct {
+    int64_t n_rhs, n_steps, n_reject, n_sigma, n_power_iter;
+    int32_t s_max_used;      /* largest RKC stage count any cell used */
+    int32_t n_failed;        /* cells whose status is not RKC_CELL_OK */
+    int32_t worst_status;    /* largest per-cell status code */
+    int32_t lanes_per_cell;  /* variant that ran */
+    int32_t schedule;        /* schedule that ran */
+    int32_t grid_blocks;     /* workgroups launched */
+    int32_t block_threads;   /* threads per workgroup */
+    int32_t lds_bytes;       /* dynamic LDS per workgroup */
+} rkc_stats;
+
+/* Fill *opts with the defaults.  Returns RKC_EINVAL for NULL. */
+int rkc_opts_default(rkc_opts *opts);
+
+/* Validate a mechanism, pack its tables and upload them to the current HIP
+ * device.  On success *out owns device memory until rkc_mech_destroy.
+ * Errors: RKC_EINVAL (sizes < 1, index out of range, > 3 molecules per side,
+ * W <= 0, non-finite parameter, A < 0), RKC_ENOTSUP (n_species > 1021),
+ * RKC_ENOMEM, RKC_EDEVICE. */
+int rkc_mech_create(const rkc_mech_desc *desc, rkc_mech **out);
+
+/* Release a mechanism; NULL is accepted. */
+int rkc_mech_destroy(rkc_mech *mech);
+
+/* Sizes of a created mechanism: species, reactions, reaction units (pairs
+ * plus unpaired reactions) and nonzero stoichiometric entries of the net
+ * production sum (E:spec-rate).  Any pointer may be NULL. */
+int rkc_mech_info(const rkc_mech *mech, int32_t *n_species, int32_t *n_reactions,
+                  int32_t *n_units, int32_t *nnz);
+
+/* Source term f(y) of E:mass and E:energy for n cells:
+ *   T [n], P [n], Y [n][n_species]  ->  f [n][n_species + 1]
+ * with f[i][0] = dT/dt and f[i][1 + k] = dY_k/dt.  Same lane-group variants
+ * as rkc_integrate (opts->lanes_per_cell).  n = 0 is a no-op. */
+int rkc_rhs(const rkc_mech *mech, size_t n, const double *T, const double *P,
+            const double *Y, double *f, const rkc_opts *opts);
+
+/* Integrate every cell from 0 to dt at constant pressure.
+ *   T [n_cells]               in: initial temperature; out: temperature at dt
+ *   P [n_cells]               pressure, unchanged
+ *   Y [n_cells][n_species]    in: initial mass fractions; out: at dt
+ *   dt > 0, rtol > 0, atol >= 0   (RKCK uses rtol as its tolerance and ignores atol)
+ *   cell_status [n_cells]     optional per-cell RKC_CELL_* codes
+ *   stats                     optional aggregate statistics (synchronises)
+ * A failed cell keeps its last accepted state (its input for BADINPUT) and
+ * never affects other cells.  Results of a cell do not depend on the
+ * schedule, the workgroup size, the grid size or the other cells in the call;
+ * they depend on lanes_per_cell only through summation order (rounding).
+ * Returns RKC_OK, RKC_ECELLS (some cell failed; only known when the call
+ * synchronises, i.e. host arrays or stats != NULL), RKC_EINVAL, RKC_ENOTSUP,
+ * RKC_ENOMEM or RKC_EDEVICE.  n_cells = 0 is a no-op. */
+int rkc_integrate(const rkc_mech *mech, size_t n_cells, double *T, const double *P,
+                  double *Y, double dt, double rtol, double atol, const rkc_opts *opts,
+                  int32_t *cell_status, rkc_stats *stats);
+
+/* Static string for a return code. */
+const char *rkc_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RKC_H */

@@ -203,7 +203,7 @@ void orc_rkc_coeffs(int s, double *mu_t, double *mu, double *nu, double *gam_t) 
     const double w1 = Tp[s] / Tpp[s];
     for (int j = 2; j <= s; ++j) b[j] = Tpp[j] / (Tp[j] * Tp[j]);
     b[1] = 1.0 / w0;
-    b[0] = b[2];
+    b[0] = (s >= 2) ? b[2] : 0.0;
     for (int j = 0; j <= s; ++j) a[j] = 1.0 - b[j] * Tc[j];
     mu_t[1] = b[1] * w1;
     for (int j = 2; j <= s; ++j) {

@@ -1,0 +1,559 @@
+// Host runtime of the C ABI declared in include/rkc.h: mechanism packing and
+// upload, variant selection, launch configuration and host<->device staging.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "rkc.h"
+#include "rkc_internal.h"
+
+using rkcdev::NFIELD;
+using rkcdev::UNIT_DOUBLES;
+
+namespace {
+
+constexpr double R_J = 8.31446261815324;   // J/(mol K)
+constexpr double LNA_ZERO = -1e300;        // ln A of a reaction whose rate is identically 0
+
+struct NkTables {
+    int NK = 0;
+    double *spec = nullptr;
+    int32_t *ent = nullptr;
+    int32_t *rowptr = nullptr;
+};
+
+}  // namespace
+
+struct rkc_mech {
+    int device = 0;
+    int nS = 0, nR = 0, N = 0, nU = 0, nU_pad = 0, nnz = 0, max_row = 0;
+    std::vector<double> units_h;                       // [nU_pad][8]
+    std::vector<double> W, lo, hi, Tmid;               // species data
+    std::vector<std::vector<std::pair<int, int>>> rows;  // species -> (unit, dnu)
+    double *units_d = nullptr;
+    std::vector<NkTables> nk;
+    unsigned long long *agg_d = nullptr;               // [8]
+    int *queue_d = nullptr;
+    void *stage_d = nullptr;
+    size_t stage_bytes = 0;
+    int num_cus = 0;
+    size_t max_lds = 0;
+};
+
+namespace {
+
+int count_in(const int32_t *slots, int sp) {
+    int c = 0;
+    for (int s = 0; s < 3; ++s) c += (slots[s] == sp);
+    return c;
+}
+
+bool same_multiset(const int32_t *a, const int32_t *b) {
+    int x[3], y[3];
+    for (int s = 0; s < 3; ++s) { x[s] = a[s]; y[s] = b[s]; }
+    std::sort(x, x + 3);
+    std::sort(y, y + 3);
+    return x[0] == y[0] && x[1] == y[1] && x[2] == y[2];
+}
+
+uint32_t pack_slots(const int32_t *slots, int nS) {
+    uint32_t v = 0;
+    for (int s = 0; s < 3; ++s) {
+        const uint32_t id = slots[s] >= 0 ? (uint32_t)slots[s] : (uint32_t)nS;
+        v |= id << (10 * s);
+    }
+    return v;
+}
+
+double ln_a(double A) { return A > 0.0 ? std::log(A) : LNA_ZERO; }
+
+#define HIP_OK(expr)                                          \
+    do {                                                      \
+        if ((expr) != hipSuccess) return RKC_EDEVICE;         \
+    } while (0)
+
+int ensure_nk(rkc_mech *m, int NK, NkTables **out) {
+    for (auto &t : m->nk)
+        if (t.NK == NK) { *out = &t; return RKC_OK; }
+    const int nS = m->nS;
+    std::vector<double> spec((size_t)NFIELD * NK, 0.0);
+    for (int i = 0; i < nS; ++i) {
+        const int k = i + 1;
+        auto put = [&](int f, double v) { spec[(size_t)f * NK + k] = v; };
+        put(rkcdev::F_W, m->W[i]);
+        put(rkcdev::F_INVW, 1.0 / m->W[i]);
+        put(rkcdev::F_TMID, m->Tmid[i]);
+        const double *a[2] = {&m->lo[7 * i], &m->hi[7 * i]};
+        const int cpo[2] = {rkcdev::F_CPLO, rkcdev::F_CPHI};
+        const int ho[2] = {rkcdev::F_HLO, rkcdev::F_HHI};
+        for (int r = 0; r < 2; ++r) {
+            for (int q = 0; q < 5; ++q) put(cpo[r] + q, a[r][q]);
+            put(ho[r] + 0, a[r][0]);
+            put(ho[r] + 1, a[r][1] / 2.0);
+            put(ho[r] + 2, a[r][2] / 3.0);
+            put(ho[r] + 3, a[r][3] / 4.0);
+            put(ho[r] + 4, a[r][4] / 5.0);
+            put(ho[r] + 5, a[r][5]);
+        }
+    }
+    // species-major CSR over state indices: row k = i + 1 lists species i's entries
+    std::vector<int32_t> ent, rowptr(NK + 1, 0);
+    ent.reserve(std::max(1, m->nnz));
+    for (int k = 0; k < NK; ++k) {
+        rowptr[k] = (int32_t)ent.size();
+        if (k >= 1 && k <= nS)
+            for (const auto &pr : m->rows[k - 1]) ent.push_back((pr.first << 8) | (pr.second + 128));
+    }
+    rowptr[NK] = (int32_t)ent.size();
+    if (ent.empty()) ent.push_back(0);
+    NkTables t;
+    t.NK = NK;
+    if (hipMalloc(&t.spec, spec.size() * 8) != hipSuccess) return RKC_ENOMEM;
+    if (hipMalloc(&t.ent, ent.size() * 4) != hipSuccess) { (void)hipFree(t.spec); return RKC_ENOMEM; }
+    if (hipMalloc(&t.rowptr, rowptr.size() * 4) != hipSuccess) {
+        (void)hipFree(t.spec); (void)hipFree(t.ent); return RKC_ENOMEM;
+    }
+    HIP_OK(hipMemcpy(t.spec, spec.data(), spec.size() * 8, hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(t.ent, ent.data(), ent.size() * 4, hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(t.rowptr, rowptr.data(), rowptr.size() * 4, hipMemcpyHostToDevice));
+    m->nk.push_back(t);
+    *out = &m->nk.back();
+    return RKC_OK;
+}
+
+struct Choice {
+    rkchost::VariantDesc v;
+    int RU;
+};
+
+int choose_variant(const rkc_mech *m, int lanes, Choice *out) {
+    int G = lanes;
+    if (G == 0) G = (m->N >= 40) ? 64 : (m->N > 16 ? 32 : 16);
+    int n = 0;
+    const rkchost::VariantDesc *tab = nullptr;
+    switch (G) {
+    case 64: tab = rkchost::variants_g64(&n); break;
+    case 32: tab = rkchost::variants_g32(&n); break;
+    case 16: tab = rkchost::variants_g16(&n); break;
+    case 8: tab = rkchost::variants_g8(&n); break;
+    default: return RKC_EINVAL;
+    }
+    const int nsl_need = (m->N + G - 1) / G;
+    const int ru = std::max(1, (m->nU + G - 1) / G);
+    int best_nsl = 1 << 30;
+    for (int i = 0; i < n; ++i)
+        if (tab[i].NSL >= nsl_need) best_nsl = std::min(best_nsl, tab[i].NSL);
+    if (best_nsl == (1 << 30)) return RKC_ENOTSUP;
+    const rkchost::VariantDesc *pick = nullptr;
+    for (int i = 0; i < n; ++i)
+        if (tab[i].NSL == best_nsl && tab[i].RUC == ru) pick = &tab[i];
+    if (!pick)
+        for (int i = 0; i < n; ++i)
+            if (tab[i].NSL == best_nsl && tab[i].RUC == 0) pick = &tab[i];
+    if (!pick) return RKC_ENOTSUP;
+    out->v = *pick;
+    out->RU = ru;
+    return RKC_OK;
+}
+
+int ensure_stage(rkc_mech *m, size_t bytes) {
+    if (m->stage_bytes >= bytes) return RKC_OK;
+    if (m->stage_d) (void)hipFree(m->stage_d);
+    m->stage_d = nullptr;
+    m->stage_bytes = 0;
+    if (hipMalloc(&m->stage_d, bytes) != hipSuccess) return RKC_ENOMEM;
+    m->stage_bytes = bytes;
+    return RKC_OK;
+}
+
+__global__ void reset_scratch_kernel(unsigned long long *agg, int *queue) {
+    if (threadIdx.x < 8) agg[threadIdx.x] = 0ull;
+    if (threadIdx.x == 0) *queue = 0;
+}
+
+struct Launch {
+    int threads, blocks, groups_per_block;
+    size_t lds;
+    bool persistent;
+};
+
+int plan_launch(const rkc_mech *m, const Choice &ch, const void *kernel, size_t n_cells,
+                const rkc_opts &o, bool allow_persistent, NkTables *nk, Launch *L) {
+    const int G = ch.v.G;
+    const int NK = nk->NK;
+    int gpb = o.block_groups > 0 ? o.block_groups : std::max(1, 256 / G);
+    if (gpb * G > 512) gpb = 512 / G;
+    auto need = [&](int groups) {
+        return rkcdev::lds_bytes(NK, ch.RU, G, std::max(1, m->nnz), groups, ch.v.RUC == 0);
+    };
+    while (gpb > 1 && need(gpb) > m->max_lds) gpb = (gpb + 1) / 2;
+    if (need(gpb) > m->max_lds) return RKC_ENOTSUP;
+    L->groups_per_block = gpb;
+    L->threads = gpb * G;
+    L->lds = need(gpb);
+    if (hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L->lds) !=
+        hipSuccess)
+        return RKC_EDEVICE;
+    const size_t blocks_all = (n_cells + gpb - 1) / gpb;
+    L->persistent = false;
+    size_t blocks = blocks_all;
+    const int sched = o.schedule;
+    if (allow_persistent && sched != RKC_SCHED_PLAIN) {
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, L->threads, L->lds) !=
+            hipSuccess)
+            return RKC_EDEVICE;
+        per_cu = std::max(1, per_cu);
+        size_t resident = (size_t)per_cu * (size_t)m->num_cus;
+        if (o.grid_blocks > 0) resident = (size_t)o.grid_blocks;
+        if (sched == RKC_SCHED_PERSISTENT || resident < blocks_all) {
+            L->persistent = true;
+            blocks = std::min(blocks_all, resident);
+        }
+    }
+    if (blocks > 0x7fffffff) return RKC_ENOTSUP;
+    L->blocks = (int)std::max<size_t>(1, blocks);
+    return RKC_OK;
+}
+
+void fill_params(const rkc_mech *m, const Choice &ch, const NkTables *nk, rkcdev::Params *p) {
+    std::memset(p, 0, sizeof(*p));
+    p->nS = m->nS;
+    p->N = m->N;
+    p->NK = nk->NK;
+    p->nU = m->nU;
+    p->RU = ch.RU;
+    p->nnz = std::max(1, m->nnz);
+    p->tab.units = m->units_d;
+    p->tab.spec = nk->spec;
+    p->tab.ent = nk->ent;
+    p->tab.row_ptr = nk->rowptr;
+    p->agg = m->agg_d;
+    p->queue = m->queue_d;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rkc_opts_default(rkc_opts *o) {
+    if (!o) return RKC_EINVAL;
+    std::memset(o, 0, sizeof(*o));
+    o->method = RKC_METHOD_RKC;
+    o->s_max = 1000;
+    o->max_steps = 1000000;
+    o->schedule = RKC_SCHED_AUTO;
+    return RKC_OK;
+}
+
+const char *rkc_strerror(int code) {
+    switch (code) {
+    case RKC_OK: return "ok";
+    case RKC_EINVAL: return "invalid argument";
+    case RKC_ENOMEM: return "out of memory";
+    case RKC_EDEVICE: return "HIP runtime error";
+    case RKC_ECELLS: return "some cells failed";
+    case RKC_ENOTSUP: return "mechanism or option not supported by the compiled variants";
+    default: return "unknown error";
+    }
+}
+
+int rkc_mech_destroy(rkc_mech *m) {
+    if (!m) return RKC_OK;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipSetDevice(m->device);
+    if (m->units_d) (void)hipFree(m->units_d);
+    for (auto &t : m->nk) {
+        (void)hipFree(t.spec);
+        (void)hipFree(t.ent);
+        (void)hipFree(t.rowptr);
+    }
+    if (m->agg_d) (void)hipFree(m->agg_d);
+    if (m->queue_d) (void)hipFree(m->queue_d);
+    if (m->stage_d) (void)hipFree(m->stage_d);
+    (void)hipSetDevice(dev);
+    delete m;
+    return RKC_OK;
+}
+
+int rkc_mech_create(const rkc_mech_desc *d, rkc_mech **out) {
+    if (!d || !out) return RKC_EINVAL;
+    *out = nullptr;
+    const int nS = d->n_species, nR = d->n_reactions;
+    if (nS < 1 || nR < 0) return RKC_EINVAL;
+    if (nS > 1021) return RKC_ENOTSUP;
+    if (!d->W || !d->nasa_low || !d->nasa_high || !d->T_mid) return RKC_EINVAL;
+    if (nR > 0 && (!d->reac || !d->prod || !d->A || !d->beta || !d->Ea)) return RKC_EINVAL;
+    for (int i = 0; i < nS; ++i) {
+        if (!(d->W[i] > 0.0) || !std::isfinite(d->W[i]) || !std::isfinite(d->T_mid[i]))
+            return RKC_EINVAL;
+        for (int q = 0; q < 7; ++q)
+            if (!std::isfinite(d->nasa_low[7 * i + q]) || !std::isfinite(d->nasa_high[7 * i + q]))
+                return RKC_EINVAL;
+    }
+    for (int j = 0; j < nR; ++j) {
+        if (!(d->A[j] >= 0.0) || !std::isfinite(d->A[j]) || !std::isfinite(d->beta[j]) ||
+            !std::isfinite(d->Ea[j]))
+            return RKC_EINVAL;
+        for (int s = 0; s < 3; ++s) {
+            const int a = d->reac[3 * j + s], b = d->prod[3 * j + s];
+            if (a < -1 || a >= nS || b < -1 || b >= nS) return RKC_EINVAL;
+        }
+    }
+    rkc_mech *m = new (std::nothrow) rkc_mech();
+    if (!m) return RKC_ENOMEM;
+    m->nS = nS;
+    m->nR = nR;
+    m->N = nS + 1;
+    m->W.assign(d->W, d->W + nS);
+    m->lo.assign(d->nasa_low, d->nasa_low + 7 * nS);
+    m->hi.assign(d->nasa_high, d->nasa_high + 7 * nS);
+    m->Tmid.assign(d->T_mid, d->T_mid + nS);
+    m->rows.assign(nS, {});
+
+    // Reaction units: a reaction immediately followed by its exact reverse is
+    // one unit with net rate of progress; any other reaction is a unit alone.
+    std::vector<double> units;
+    int p = 0;
+    for (int j = 0; j < nR; ++p) {
+        const int32_t *rf = d->reac + 3 * j, *pf = d->prod + 3 * j;
+        const bool pair = (j + 1 < nR) && same_multiset(d->reac + 3 * (j + 1), pf) &&
+                          same_multiset(d->prod + 3 * (j + 1), rf);
+        double rec[UNIT_DOUBLES] = {0};
+        rec[0] = ln_a(d->A[j]);
+        rec[1] = d->beta[j];
+        rec[2] = d->Ea[j] / R_J;
+        uint64_t idr = 0;
+        if (pair) {
+            rec[3] = ln_a(d->A[j + 1]);
+            rec[4] = d->beta[j + 1];
+            rec[5] = d->Ea[j + 1] / R_J;
+            idr = pack_slots(d->reac + 3 * (j + 1), nS);
+        } else {
+            rec[3] = LNA_ZERO;
+            const int32_t none[3] = {-1, -1, -1};
+            idr = pack_slots(none, nS);
+        }
+        const uint64_t bits = (uint64_t)pack_slots(rf, nS) | (idr << 32);
+        std::memcpy(&rec[6], &bits, 8);
+        units.insert(units.end(), rec, rec + UNIT_DOUBLES);
+        for (int i = 0; i < nS; ++i) {
+            const int dnu = count_in(pf, i) - count_in(rf, i);
+            if (dnu != 0) m->rows[i].push_back({p, dnu});
+        }
+        j += pair ? 2 : 1;
+    }
+    m->nU = p;
+    m->nU_pad = std::max(64, (p + 63) / 64 * 64);
+    if (m->nU_pad >= (1 << 23)) { delete m; return RKC_ENOTSUP; }
+    // padding units: zero parameters and empty slots -> net rate 1 - 1 = 0, never gathered
+    double pad[UNIT_DOUBLES] = {0};
+    {
+        const int32_t none[3] = {-1, -1, -1};
+        const uint64_t bits = (uint64_t)pack_slots(none, nS) | ((uint64_t)pack_slots(none, nS) << 32);
+        std::memcpy(&pad[6], &bits, 8);
+    }
+    for (int q = p; q < m->nU_pad; ++q) units.insert(units.end(), pad, pad + UNIT_DOUBLES);
+    m->units_h = units;
+    for (int i = 0; i < nS; ++i) {
+        m->nnz += (int)m->rows[i].size();
+        m->max_row = std::max(m->max_row, (int)m->rows[i].size());
+    }
+
+    int rc = RKC_OK;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&m->device) != hipSuccess ||
+        hipGetDeviceProperties(&prop, m->device) != hipSuccess) {
+        rc = RKC_EDEVICE;
+    } else {
+        m->num_cus = prop.multiProcessorCount;
+        m->max_lds = prop.sharedMemPerBlock;
+        if (hipMalloc(&m->units_d, m->units_h.size() * 8) != hipSuccess ||
+            hipMalloc(&m->agg_d, 8 * sizeof(unsigned long long)) != hipSuccess ||
+            hipMalloc(&m->queue_d, sizeof(int)) != hipSuccess)
+            rc = RKC_ENOMEM;
+        else if (hipMemcpy(m->units_d, m->units_h.data(), m->units_h.size() * 8,
+                           hipMemcpyHostToDevice) != hipSuccess)
+            rc = RKC_EDEVICE;
+    }
+    if (rc != RKC_OK) {
+        rkc_mech_destroy(m);
+        return rc;
+    }
+    *out = m;
+    return RKC_OK;
+}
+
+int rkc_mech_info(const rkc_mech *m, int32_t *n_species, int32_t *n_reactions, int32_t *n_units,
+                  int32_t *nnz) {
+    if (!m) return RKC_EINVAL;
+    if (n_species) *n_species = m->nS;
+    if (n_reactions) *n_reactions = m->nR;
+    if (n_units) *n_units = m->nU;
+    if (nnz) *nnz = m->nnz;
+    return RKC_OK;
+}
+
+int rkc_rhs(const rkc_mech *mc, size_t n, const double *T, const double *P, const double *Y,
+            double *f, const rkc_opts *opts) {
+    if (!mc) return RKC_EINVAL;
+    rkc_mech *m = const_cast<rkc_mech *>(mc);
+    rkc_opts o;
+    if (opts) o = *opts; else rkc_opts_default(&o);
+    if (n == 0) return RKC_OK;
+    if (!T || !P || !Y || !f) return RKC_EINVAL;
+    if (n > 0x7fffffff) return RKC_ENOTSUP;
+    int cur = 0;
+    HIP_OK(hipGetDevice(&cur));
+    if (cur != m->device) HIP_OK(hipSetDevice(m->device));
+    Choice ch;
+    int rc = choose_variant(m, o.lanes_per_cell, &ch);
+    if (rc) return rc;
+    NkTables *nk = nullptr;
+    rc = ensure_nk(m, ch.v.NSL * ch.v.G, &nk);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)o.stream;
+    const double *Td = T, *Pd = P, *Yd = Y;
+    double *fd = f;
+    const size_t N = (size_t)m->N, nS = (size_t)m->nS;
+    if (!o.device_ptrs) {
+        const size_t bytes = 8 * n * (2 + nS + N);
+        rc = ensure_stage(m, bytes);
+        if (rc) return rc;
+        double *b = (double *)m->stage_d;
+        double *Tb = b, *Pb = b + n, *Yb = b + 2 * n;
+        fd = b + 2 * n + n * nS;
+        HIP_OK(hipMemcpyAsync(Tb, T, 8 * n, hipMemcpyHostToDevice, st));
+        HIP_OK(hipMemcpyAsync(Pb, P, 8 * n, hipMemcpyHostToDevice, st));
+        HIP_OK(hipMemcpyAsync(Yb, Y, 8 * n * nS, hipMemcpyHostToDevice, st));
+        Td = Tb; Pd = Pb; Yd = Yb;
+    }
+    rkc_opts lo = o;
+    lo.schedule = RKC_SCHED_PLAIN;
+    Launch L;
+    rc = plan_launch(m, ch, ch.v.k_rhs, n, lo, false, nk, &L);
+    if (rc) return rc;
+    rkcdev::Params p;
+    fill_params(m, ch, nk, &p);
+    p.n_cells = (int)n;
+    p.T = const_cast<double *>(Td);
+    p.P = Pd;
+    p.Y = const_cast<double *>(Yd);
+    p.F = fd;
+    void *args[] = {&p};
+    HIP_OK(hipLaunchKernel(ch.v.k_rhs, dim3(L.blocks), dim3(L.threads), args, L.lds, st));
+    if (!o.device_ptrs) {
+        HIP_OK(hipMemcpyAsync(f, fd, 8 * n * N, hipMemcpyDeviceToHost, st));
+        HIP_OK(hipStreamSynchronize(st));
+    }
+    return RKC_OK;
+}
+
+int rkc_integrate(const rkc_mech *mc, size_t n, double *T, const double *P, double *Y,
+                  double dt, double rtol, double atol, const rkc_opts *opts,
+                  int32_t *cell_status, rkc_stats *stats) {
+    if (!mc) return RKC_EINVAL;
+    rkc_mech *m = const_cast<rkc_mech *>(mc);
+    rkc_opts o;
+    if (opts) o = *opts; else rkc_opts_default(&o);
+    if (!(dt > 0.0) || !std::isfinite(dt) || !(rtol > 0.0) || !std::isfinite(rtol) ||
+        !(atol >= 0.0) || !std::isfinite(atol))
+        return RKC_EINVAL;
+    if (o.method != RKC_METHOD_RKC && o.method != RKC_METHOD_RKCK) return RKC_EINVAL;
+    if (o.s_max < 2 || o.max_steps < 1) return RKC_EINVAL;
+    if (o.schedule < 0 || o.schedule > 2 || o.block_groups < 0 || o.grid_blocks < 0)
+        return RKC_EINVAL;
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    if (n == 0) return RKC_OK;
+    if (!T || !P || !Y) return RKC_EINVAL;
+    if (n > 0x7fffffff) return RKC_ENOTSUP;
+    int cur = 0;
+    HIP_OK(hipGetDevice(&cur));
+    if (cur != m->device) HIP_OK(hipSetDevice(m->device));
+    Choice ch;
+    int rc = choose_variant(m, o.lanes_per_cell, &ch);
+    if (rc) return rc;
+    NkTables *nk = nullptr;
+    rc = ensure_nk(m, ch.v.NSL * ch.v.G, &nk);
+    if (rc) return rc;
+    const void *kernel = o.method == RKC_METHOD_RKC ? ch.v.k_rkc : ch.v.k_rkck;
+    Launch L;
+    rc = plan_launch(m, ch, kernel, n, o, true, nk, &L);
+    if (rc) return rc;
+
+    hipStream_t st = (hipStream_t)o.stream;
+    const size_t nS = (size_t)m->nS;
+    double *Td = T, *Yd = Y;
+    const double *Pd = P;
+    int32_t *sd = cell_status, *cd = o.cell_counters;
+    if (!o.device_ptrs) {
+        const size_t bytes = 8 * n * (2 + nS) + 4 * n + (o.cell_counters ? 32 * n : 0);
+        rc = ensure_stage(m, bytes);
+        if (rc) return rc;
+        double *b = (double *)m->stage_d;
+        Td = b;
+        double *Pb = b + n;
+        Yd = b + 2 * n;
+        sd = (int32_t *)(b + 2 * n + n * nS);
+        cd = o.cell_counters ? sd + n : nullptr;
+        HIP_OK(hipMemcpyAsync(Td, T, 8 * n, hipMemcpyHostToDevice, st));
+        HIP_OK(hipMemcpyAsync(Pb, P, 8 * n, hipMemcpyHostToDevice, st));
+        HIP_OK(hipMemcpyAsync(Yd, Y, 8 * n * nS, hipMemcpyHostToDevice, st));
+        Pd = Pb;
+    }
+    hipLaunchKernelGGL(reset_scratch_kernel, dim3(1), dim3(64), 0, st, m->agg_d, m->queue_d);
+    HIP_OK(hipGetLastError());
+    rkcdev::Params p;
+    fill_params(m, ch, nk, &p);
+    p.n_cells = (int)n;
+    p.T = Td;
+    p.P = Pd;
+    p.Y = Yd;
+    p.dt = dt;
+    p.rtol = rtol;
+    p.atol = atol;
+    p.s_max = o.s_max;
+    p.max_steps = o.max_steps;
+    p.cell_status = sd;
+    p.cell_counters = cd;
+    p.persistent = L.persistent ? 1 : 0;
+    p.groups_total = L.blocks * L.groups_per_block;
+    void *args[] = {&p};
+    HIP_OK(hipLaunchKernel(kernel, dim3(L.blocks), dim3(L.threads), args, L.lds, st));
+    unsigned long long agg[8] = {0};
+    const bool sync = !o.device_ptrs || stats;
+    if (!o.device_ptrs) {
+        HIP_OK(hipMemcpyAsync(T, Td, 8 * n, hipMemcpyDeviceToHost, st));
+        HIP_OK(hipMemcpyAsync(Y, Yd, 8 * n * nS, hipMemcpyDeviceToHost, st));
+        if (cell_status) HIP_OK(hipMemcpyAsync(cell_status, sd, 4 * n, hipMemcpyDeviceToHost, st));
+        if (o.cell_counters)
+            HIP_OK(hipMemcpyAsync(o.cell_counters, cd, 32 * n, hipMemcpyDeviceToHost, st));
+    }
+    if (sync) {
+        HIP_OK(hipMemcpyAsync(agg, m->agg_d, sizeof(agg), hipMemcpyDeviceToHost, st));
+        HIP_OK(hipStreamSynchronize(st));
+    }
+    if (stats) {
+        stats->n_rhs = (int64_t)agg[0];
+        stats->n_steps = (int64_t)agg[1];
+        stats->n_reject = (int64_t)agg[2];
+        stats->n_sigma = (int64_t)agg[3];
+        stats->n_power_iter = (int64_t)agg[4];
+        stats->s_max_used = (int32_t)agg[5];
+        stats->n_failed = (int32_t)agg[6];
+        stats->worst_status = (int32_t)agg[7];
+        stats->lanes_per_cell = ch.v.G;
+        stats->schedule = L.persistent ? RKC_SCHED_PERSISTENT : RKC_SCHED_PLAIN;
+        stats->grid_blocks = L.blocks;
+        stats->block_threads = L.threads;
+        stats->lds_bytes = (int32_t)L.lds;
+    }
+    if (sync && agg[6] > 0) return RKC_ECELLS;
+    return RKC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,14 @@
+// Kernel variants with 8 lanes per cell.
+#include "rkc_integrate.h"
+#include "rkc_internal.h"
+
+namespace rkchost {
+
+static const VariantDesc kTable[] = {RKC_VARIANT(8, 2, 3), RKC_VARIANT(8, 2, 4), RKC_VARIANT(8, 2, 0), RKC_VARIANT(8, 4, 0)};
+
+const VariantDesc *variants_g8(int *n) {
+    *n = (int)(sizeof(kTable) / sizeof(kTable[0]));
+    return kTable;
+}
+
+}  // namespace rkchost

@@ -1,0 +1,255 @@
+"""Python binding of the C ABI in include/rkc.h (argument marshalling only).
+
+Every step of the integration runs in the HIP library librkc.so; this module
+only converts numpy arrays or torch tensors into pointers.  If the library is
+missing the import of `lib()` fails loudly: there is no CPU fallback.
+
+Arrays:
+  numpy arrays      -> host pointers (the library stages them on the device)
+  torch GPU tensors -> device pointers (work is enqueued on the tensor's
+                       current stream, or on the stream passed explicitly)
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librkc.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ECELLS, ENOTSUP = 0, -1, -2, -3, -4, -5
+CELL_OK, CELL_UNDERFLOW, CELL_MAXSTEPS, CELL_NONFINITE, CELL_BADINPUT = 0, 1, 2, 3, 4
+RKC, RKCK = 0, 1
+SCHED_AUTO, SCHED_PLAIN, SCHED_PERSISTENT = 0, 1, 2
+NCOUNTERS = 8
+COUNTER_FIELDS = ["n_rhs", "n_steps", "n_reject", "n_sigma", "s_max_used", "s_hash", "status",
+                  "n_power_iter"]
+
+EXPORTED = ["rkc_opts_default", "rkc_mech_create", "rkc_mech_destroy", "rkc_mech_info",
+            "rkc_rhs", "rkc_integrate", "rkc_strerror"]
+
+
+class MechDesc(ct.Structure):
+    _fields_ = [("n_species", ct.c_int32), ("n_reactions", ct.c_int32),
+                ("W", ct.c_void_p), ("nasa_low", ct.c_void_p), ("nasa_high", ct.c_void_p),
+                ("T_mid", ct.c_void_p), ("reac", ct.c_void_p), ("prod", ct.c_void_p),
+                ("A", ct.c_void_p), ("beta", ct.c_void_p), ("Ea", ct.c_void_p)]
+
+
+class Opts(ct.Structure):
+    _fields_ = [("method", ct.c_int32), ("s_max", ct.c_int32), ("max_steps", ct.c_int32),
+                ("lanes_per_cell", ct.c_int32), ("schedule", ct.c_int32),
+                ("block_groups", ct.c_int32), ("grid_blocks", ct.c_int32),
+                ("device_ptrs", ct.c_int32), ("stream", ct.c_void_p),
+                ("cell_counters", ct.c_void_p)]
+
+
+class Stats(ct.Structure):
+    _fields_ = [("n_rhs", ct.c_int64), ("n_steps", ct.c_int64), ("n_reject", ct.c_int64),
+                ("n_sigma", ct.c_int64), ("n_power_iter", ct.c_int64),
+                ("s_max_used", ct.c_int32), ("n_failed", ct.c_int32),
+                ("worst_status", ct.c_int32), ("lanes_per_cell", ct.c_int32),
+                ("schedule", ct.c_int32), ("grid_blocks", ct.c_int32),
+                ("block_threads", ct.c_int32), ("lds_bytes", ct.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class RkcError(RuntimeError):
+    def __init__(self, code, what=""):
+        self.code = code
+        super().__init__("%s failed: %s (%d)" % (what, strerror(code), code))
+
+
+_lib = None
+
+
+def lib():
+    """The loaded librkc.so (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("librkc.so not built: run __graft_entry__.build() "
+                               "or python paper_1309_2710_amd/build.py")
+        L = ct.CDLL(LIB_PATH)
+        L.rkc_opts_default.argtypes = [ct.POINTER(Opts)]
+        L.rkc_mech_create.argtypes = [ct.POINTER(MechDesc), ct.POINTER(ct.c_void_p)]
+        L.rkc_mech_destroy.argtypes = [ct.c_void_p]
+        L.rkc_mech_info.argtypes = [ct.c_void_p] + [ct.POINTER(ct.c_int32)] * 4
+        L.rkc_rhs.argtypes = [ct.c_void_p, ct.c_size_t, ct.c_void_p, ct.c_void_p, ct.c_void_p,
+                              ct.c_void_p, ct.POINTER(Opts)]
+        L.rkc_integrate.argtypes = [ct.c_void_p, ct.c_size_t, ct.c_void_p, ct.c_void_p,
+                                    ct.c_void_p, ct.c_double, ct.c_double, ct.c_double,
+                                    ct.POINTER(Opts), ct.c_void_p, ct.POINTER(Stats)]
+        L.rkc_strerror.restype = ct.c_char_p
+        L.rkc_strerror.argtypes = [ct.c_int]
+        _lib = L
+    return _lib
+
+
+def strerror(code):
+    try:
+        return lib().rkc_strerror(int(code)).decode()
+    except RuntimeError:
+        return "code %d" % code
+
+
+def _np_ptr(a):
+    return a.ctypes.data_as(ct.c_void_p)
+
+
+class Mechanism:
+    """A mechanism uploaded to the current HIP device (rkc_mech_create)."""
+
+    def __init__(self, mech):
+        L = lib()
+        nS, nR = int(mech["n_species"]), int(mech["n_reactions"])
+        keep = {
+            "W": np.ascontiguousarray(mech["W"], np.float64),
+            "nasa_low": np.ascontiguousarray(mech["nasa_low"], np.float64),
+            "nasa_high": np.ascontiguousarray(mech["nasa_high"], np.float64),
+            "T_mid": np.ascontiguousarray(mech["T_mid"], np.float64),
+            "reac": np.ascontiguousarray(mech["reac"], np.int32),
+            "prod": np.ascontiguousarray(mech["prod"], np.int32),
+            "A": np.ascontiguousarray(mech["A"], np.float64),
+            "beta": np.ascontiguousarray(mech["beta"], np.float64),
+            "Ea": np.ascontiguousarray(mech["Ea"], np.float64),
+        }
+        d = MechDesc(nS, nR, *[_np_ptr(keep[k]) for k in
+                               ["W", "nasa_low", "nasa_high", "T_mid", "reac", "prod", "A",
+                                "beta", "Ea"]])
+        h = ct.c_void_p()
+        rc = L.rkc_mech_create(ct.byref(d), ct.byref(h))
+        if rc != OK:
+            raise RkcError(rc, "rkc_mech_create")
+        self._h = h
+        self.n_species = nS
+        self.n_reactions = nR
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self):
+        v = [ct.c_int32() for _ in range(4)]
+        rc = lib().rkc_mech_info(self._h, *[ct.byref(x) for x in v])
+        if rc != OK:
+            raise RkcError(rc, "rkc_mech_info")
+        return dict(zip(["n_species", "n_reactions", "n_units", "nnz"], [x.value for x in v]))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().rkc_mech_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _is_torch(x):
+    return type(x).__module__.startswith("torch")
+
+
+def make_opts(method=RKC, s_max=1000, max_steps=1000000, lanes_per_cell=0,
+              schedule=SCHED_AUTO, block_groups=0, grid_blocks=0, device_ptrs=False,
+              stream=None, cell_counters=None):
+    o = Opts()
+    lib().rkc_opts_default(ct.byref(o))
+    o.method = int(method)
+    o.s_max = int(s_max)
+    o.max_steps = int(max_steps)
+    o.lanes_per_cell = int(lanes_per_cell)
+    o.schedule = int(schedule)
+    o.block_groups = int(block_groups)
+    o.grid_blocks = int(grid_blocks)
+    o.device_ptrs = 1 if device_ptrs else 0
+    o.stream = stream
+    o.cell_counters = cell_counters
+    return o
+
+
+def _stream_handle(stream, tensors):
+    if stream is not None:
+        return ct.c_void_p(stream if isinstance(stream, int) else stream.cuda_stream)
+    import torch
+    return ct.c_void_p(torch.cuda.current_stream(tensors[0].device).cuda_stream)
+
+
+def integrate(mech, T, P, Y, dt, rtol=1e-6, atol=1e-10, method=RKC, lanes_per_cell=0,
+              schedule=SCHED_AUTO, block_groups=0, grid_blocks=0, s_max=1000,
+              max_steps=1000000, counters=False, status=True, stats=False, stream=None,
+              check=True):
+    """Integrate cells over [0, dt] in place.
+
+    numpy inputs: T [n] and Y [n][nS] are overwritten in place (must be
+    C-contiguous float64).  torch GPU inputs: the same, on the device.
+    Returns dict with optional 'status' [n] int32, 'counters' [n][8] int32,
+    'stats' (dict), 'rc'.
+    """
+    L = lib()
+    dev = _is_torch(T)
+    n = int(T.shape[0])
+    out = {}
+    if dev:
+        import torch
+        for a in (T, P, Y):
+            assert a.is_cuda and a.dtype == torch.float64 and a.is_contiguous()
+        st_t = torch.empty(n, dtype=torch.int32, device=T.device) if status else None
+        cn_t = torch.empty((n, NCOUNTERS), dtype=torch.int32, device=T.device) if counters else None
+        ptrs = [ct.c_void_p(a.data_ptr()) for a in (T, P, Y)]
+        sp = ct.c_void_p(st_t.data_ptr()) if status else None
+        cp = ct.c_void_p(cn_t.data_ptr()) if counters else None
+        strm = _stream_handle(stream, [T])
+    else:
+        for a in (T, P, Y):
+            assert isinstance(a, np.ndarray) and a.dtype == np.float64 and a.flags.c_contiguous
+        st_t = np.empty(n, np.int32) if status else None
+        cn_t = np.empty((n, NCOUNTERS), np.int32) if counters else None
+        ptrs = [_np_ptr(a) for a in (T, P, Y)]
+        sp = _np_ptr(st_t) if status else None
+        cp = _np_ptr(cn_t) if counters else None
+        strm = ct.c_void_p(stream) if isinstance(stream, int) else None
+    o = make_opts(method, s_max, max_steps, lanes_per_cell, schedule, block_groups, grid_blocks,
+                  dev, strm, cp)
+    s = Stats()
+    rc = L.rkc_integrate(mech.handle, n, ptrs[0], ptrs[1], ptrs[2], float(dt), float(rtol),
+                         float(atol), ct.byref(o), sp, ct.byref(s) if stats else None)
+    if check and rc not in (OK, ECELLS):
+        raise RkcError(rc, "rkc_integrate")
+    out["rc"] = rc
+    if status:
+        out["status"] = st_t
+    if counters:
+        out["counters"] = cn_t
+    if stats:
+        out["stats"] = s.as_dict()
+    return out
+
+
+def rhs(mech, T, P, Y, lanes_per_cell=0, stream=None):
+    """Source term f [n][nS+1] (column 0 = dT/dt) for numpy or torch GPU inputs."""
+    L = lib()
+    n = int(T.shape[0])
+    N = mech.n_species + 1
+    if _is_torch(T):
+        import torch
+        f = torch.empty((n, N), dtype=torch.float64, device=T.device)
+        ptrs = [ct.c_void_p(a.data_ptr()) for a in (T, P, Y, f)]
+        o = make_opts(lanes_per_cell=lanes_per_cell, device_ptrs=True,
+                      stream=_stream_handle(stream, [T]))
+    else:
+        f = np.empty((n, N), np.float64)
+        ptrs = [_np_ptr(np.ascontiguousarray(a, np.float64)) for a in (T, P, Y)] + [_np_ptr(f)]
+        keep = [np.ascontiguousarray(a, np.float64) for a in (T, P, Y)]
+        ptrs = [_np_ptr(a) for a in keep] + [_np_ptr(f)]
+        o = make_opts(lanes_per_cell=lanes_per_cell)
+    rc = L.rkc_rhs(mech.handle, n, *ptrs, ct.byref(o))
+    if rc != OK:
+        raise RkcError(rc, "rkc_rhs")
+    return f

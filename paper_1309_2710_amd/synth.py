@@ -4,13 +4,17 @@ The paper's mechanisms (hydrogen, H2/CO, GRI-Mech 3.0, USC Mech II) and its
 ignition-sampled initial conditions (Sec. 3, "Results and discussion") are not
 available, so every workload here is synthetic, seeded and reproducible.  The
 sizes match the paper's four mechanisms: 9/38, 13/54, 53/634 and 111/1566
-species/irreversible reactions.  Like the paper's converted mechanisms
-(Appendix A turns each reversible reaction into two irreversible ones), the
-reactions come as forward/reverse pairs, each direction with its own Arrhenius
-parameters.
+species/irreversible reactions.  Like the paper's converted mechanisms, the
+reactions come as forward/reverse pairs: a reversible reaction with a random
+forward Arrhenius rate is split into two irreversible ones, the reverse rate
+coefficient k_f / K_c(T) being fitted with Arrhenius parameters at three
+temperatures by the closed form of the paper's Appendix A.  The pairs are
+therefore (to the accuracy of that fit) consistent with the mixture's
+thermodynamics, and a cell relaxes toward chemical equilibrium.
 
 This module only draws inputs.  It evaluates no right-hand side and integrates
-nothing; the one rate-like quantity it computes is a log-space upper bound of a
+nothing.  Besides the Appendix A fit (and the equilibrium constants it needs),
+the one rate-like quantity it computes is a log-space upper bound of a
 reaction's pseudo-first-order rate, used to reject parameter draws that would
 make the system stiffer than a stated stage budget allows.
 
@@ -19,7 +23,7 @@ Units carried by every mechanism dict:
   A           (cm^3/mol)^(m-1) / s, m = number of reactant molecules
   beta        dimensionless temperature exponent
   Ea          J/mol
-  nasa_low/high  NASA 7-coefficient polynomials, Cp/R and H/(R T) forms
+  nasa_low/high  NASA 7-coefficient polynomials, Cp/R, H/(R T) and S/R forms
   T_mid       K, switch between the low and high fit ranges
   reac, prod  [n_R][3] species indices with repetition (a species listed twice
               has stoichiometric coefficient 2); -1 marks an empty slot
@@ -70,9 +74,11 @@ def _nasa_species(rng, inert=False):
         hi = np.array([2.5, 0, 0, 0, 0, 0.0, 0.0])
         lo = hi.copy()
         hf = 0.0
-        # H(298.15) = 0 for the inert monatomic species
+        # H(298.15) = 0 and S(298.15)/R = 18.6 for the inert monatomic species
         lo[5] = -2.5 * 298.15
         hi[5] = lo[5]
+        lo[6] = 18.6 - 2.5 * math.log(298.15)
+        hi[6] = lo[6]
         return lo, hi, T_mid, hf
     Tg = np.linspace(300.0, 3500.0, 161)
     while True:
@@ -102,7 +108,45 @@ def _nasa_species(rng, inert=False):
 
     lo[5] = hf / R_J - hint(lo, 298.15)
     hi[5] = lo[5] + hint(lo, T_mid) - hint(hi, T_mid)
+
+    def sint(a, T):  # integral of Cp/(R T) dT without the constant
+        return a[0] * math.log(T) + a[1] * T + a[2] * T**2 / 2 + a[3] * T**3 / 3 + a[4] * T**4 / 4
+
+    s298 = rng.uniform(20.0, 35.0)      # standard entropy S(298.15)/R
+    lo[6] = s298 - sint(lo, 298.15)
+    hi[6] = lo[6] + sint(lo, T_mid) - sint(hi, T_mid)
     return lo, hi, T_mid, hf
+
+
+def gibbs_RT(nasa_low, nasa_high, T_mid, T):
+    """G/(R T) = H/(R T) - S/R of every species at temperature T (NASA-7)."""
+    out = np.empty(len(T_mid))
+    for i in range(len(T_mid)):
+        a = nasa_high[i] if T >= T_mid[i] else nasa_low[i]
+        h = a[0] + a[1] * T / 2 + a[2] * T**2 / 3 + a[3] * T**3 / 4 + a[4] * T**4 / 5 + a[5] / T
+        s_ = a[0] * math.log(T) + a[1] * T + a[2] * T**2 / 2 + a[3] * T**3 / 3 + a[4] * T**4 / 4 + a[6]
+        out[i] = h - s_
+    return out
+
+
+def ln_kc(dnu, g_rt, T):
+    """ln K_c of a reaction with net coefficients dnu (products minus reactants)
+    at T: K_p = exp(-sum dnu G/(RT)), K_c = K_p (P_atm/(R T))^(sum dnu), cgs."""
+    return -float(dnu @ g_rt) + float(dnu.sum()) * math.log(ATM * 10.0 / (R_ERG * T))
+
+
+def fit_three_point(T3, lnk3):
+    """Arrhenius parameters (ln A, beta, T_a = E/R) through three (T, ln k) points:
+    the closed form of the paper's Appendix A (Eqs. e:beta_r, e:Tar and ln A_r)."""
+    T1, T2, T3_ = T3
+    a1, a2, a3 = lnk3
+    x1, x2, x3 = math.log(T1), math.log(T2), math.log(T3_)
+    D = x1 * T1 * (T3_ - T2) + x2 * T2 * (T1 - T3_) + x3 * T3_ * (T2 - T1)
+    beta = (a1 * T1 * (T3_ - T2) + a2 * T2 * (T1 - T3_) + a3 * T3_ * (T2 - T1)) / D
+    Ta = T1 * T2 * T3_ * (a1 * (x2 - x3) + a2 * (x3 - x1) + a3 * (x1 - x2)) / D
+    lnA = (a1 * T1 * (x2 * T2 - x3 * T3_) + a2 * T2 * (x3 * T3_ - x1 * T1)
+           + a3 * T3_ * (x1 * T1 - x2 * T2)) / D
+    return lnA, beta, Ta
 
 
 def _ln_rate_bound(lnA, beta, Ea, m, T, P_pa):
@@ -166,9 +210,47 @@ def make_mechanism(n_species, n_reactions, elements, seed, *, ea_max=2e5,
             index[size].setdefault(key, []).append(ms)
 
     n_pairs = n_reactions // 2
-    pairs = set()
+    lam_cap = ((s_target - 1) ** 2 - 1) / (1.54 * dt)
+    ln_cap = math.log(lam_cap)
+    Tg = np.linspace(T_lo, T_hi, 33)
+    T_fit = (T_lo, math.sqrt(T_lo * T_hi), T_hi)
+    g_fit = [gibbs_RT(nasa_low, nasa_high, T_mid, T) for T in T_fit]
     reac = np.full((n_reactions, 3), -1, dtype=np.int32)
     prod = np.full((n_reactions, 3), -1, dtype=np.int32)
+    A = np.zeros(n_reactions)
+    beta = np.zeros(n_reactions)
+    Ea = np.zeros(n_reactions)
+
+    def dnu_of(r_ms, p_ms):
+        d = np.zeros(n_species)
+        for sp in r_ms:
+            d[sp] -= 1
+        for sp in p_ms:
+            d[sp] += 1
+        return d
+
+    def draw_params(r_ms, p_ms, tries):
+        """Forward rate drawn from the configured distributions; the reverse
+        rate k_f / K_c fitted at three temperatures (Appendix A closed form).
+        Both must respect the stiffness cap.  None if no draw passes."""
+        dnu = dnu_of(r_ms, p_ms)
+        lnkc = [ln_kc(dnu, g_fit[q], T_fit[q]) for q in range(3)]
+        for _ in range(tries):
+            lA = rng.uniform(6.0, 14.0) * math.log(10.0)
+            b = rng.uniform(-2.0, 2.0)
+            e = rng.uniform(0.0, ea_max)
+            if _ln_rate_bound(lA, b, e, len(r_ms), Tg, P_max).max() > ln_cap:
+                continue
+            lnkf = [lA + b * math.log(T) - e / (R_J * T) for T in T_fit]
+            lAr, br, Tar = fit_three_point(T_fit, [lnkf[q] - lnkc[q] for q in range(3)])
+            if not (-300.0 < lAr < 300.0):
+                continue
+            if _ln_rate_bound(lAr, br, Tar * R_J, len(p_ms), Tg, P_max).max() > ln_cap:
+                continue
+            return (math.exp(lA), b, e), (math.exp(lAr), br, Tar * R_J)
+        return None
+
+    pairs = set()
     guard = 0
     p = 0
     while p < n_pairs:
@@ -186,30 +268,22 @@ def make_mechanism(n_species, n_reactions, elements, seed, *, ea_max=2e5,
         pk = (min(r_ms, p_ms), max(r_ms, p_ms))
         if pk in pairs:
             continue
+        # write the thermodynamically favoured direction (K_c >= 1 at the
+        # middle fit temperature) first
+        if ln_kc(dnu_of(r_ms, p_ms), g_fit[1], T_fit[1]) < 0.0:
+            r_ms, p_ms = p_ms, r_ms
+        got = draw_params(r_ms, p_ms, 2000)
+        if got is None:
+            continue
         pairs.add(pk)
-        reac[2 * p, :m] = r_ms
-        prod[2 * p, :q] = p_ms
-        reac[2 * p + 1, :q] = p_ms
-        prod[2 * p + 1, :m] = r_ms
+        reac[2 * p, :len(r_ms)] = r_ms
+        prod[2 * p, :len(p_ms)] = p_ms
+        reac[2 * p + 1, :len(p_ms)] = p_ms
+        prod[2 * p + 1, :len(r_ms)] = r_ms
+        (A[2 * p], beta[2 * p], Ea[2 * p]), (A[2 * p + 1], beta[2 * p + 1], Ea[2 * p + 1]) = got
         p += 1
-
-    lam_cap = ((s_target - 1) ** 2 - 1) / (1.54 * dt)
-    ln_cap = math.log(lam_cap)
-    Tg = np.linspace(T_lo, T_hi, 33)
-    A = np.zeros(n_reactions)
-    beta = np.zeros(n_reactions)
-    Ea = np.zeros(n_reactions)
     msize = (reac >= 0).sum(axis=1)
-    for j in range(n_reactions):
-        for _ in range(100000):
-            lA = rng.uniform(6.0, 14.0) * math.log(10.0)
-            b = rng.uniform(-2.0, 2.0)
-            e = rng.uniform(0.0, ea_max)
-            if _ln_rate_bound(lA, b, e, msize[j], Tg, P_max).max() <= ln_cap:
-                break
-        else:
-            raise RuntimeError("stiffness cap unreachable")
-        A[j], beta[j], Ea[j] = math.exp(lA), b, e
+
     # keep at least 10 % of reactions active (rate >= 1e-3/dt at T_hi)
     ln_act = math.log(1e-3 / dt)
 
@@ -220,14 +294,13 @@ def make_mechanism(n_species, n_reactions, elements, seed, *, ea_max=2e5,
     act = np.array([active(j) for j in range(n_reactions)])
     tries = 0
     while act.mean() < 0.10 and tries < 100 * n_reactions:
-        j = int(rng.choice(np.flatnonzero(~act)))
-        lA = rng.uniform(6.0, 14.0) * math.log(10.0)
-        b = rng.uniform(-2.0, 2.0)
-        e = rng.uniform(0.0, ea_max)
+        j = 2 * (int(rng.choice(np.flatnonzero(~act))) // 2)
         tries += 1
-        if _ln_rate_bound(lA, b, e, msize[j], Tg, P_max).max() <= ln_cap:
-            A[j], beta[j], Ea[j] = math.exp(lA), b, e
-            act[j] = active(j)
+        got = draw_params(tuple(x for x in reac[j] if x >= 0), tuple(x for x in prod[j] if x >= 0),
+                          2000)
+        if got is not None:
+            (A[j], beta[j], Ea[j]), (A[j + 1], beta[j + 1], Ea[j + 1]) = got
+            act[j], act[j + 1] = active(j), active(j + 1)
 
     names = []
     for i in range(n_species):
@@ -253,6 +326,7 @@ def make_mechanism(n_species, n_reactions, elements, seed, *, ea_max=2e5,
         "beta": beta,
         "Ea": Ea,
         "lambda_cap": lam_cap,
+        "T_fit": T_fit,
         "active_fraction": float(act.mean()),
     }
 

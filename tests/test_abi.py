@@ -1,0 +1,85 @@
+"""CPU checks of the C ABI library: it loads, exports every function that
+include/rkc.h declares, and rejects bad arguments before touching a device."""
+import ctypes as ct
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1309_2710_amd import rkc, synth
+
+HDR = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "rkc.h")
+
+
+def _declared():
+    txt = open(HDR).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(rkc_[a-z_]+)\s*\(", txt)))
+
+
+def test_header_declares_expected_entry_points():
+    assert _declared() == sorted(rkc.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    L = rkc.lib()
+    for name in _declared():
+        assert hasattr(L, name), name
+
+
+def test_defaults_and_strings():
+    o = rkc.Opts()
+    assert rkc.lib().rkc_opts_default(ct.byref(o)) == rkc.OK
+    assert (o.method, o.s_max, o.max_steps, o.schedule, o.device_ptrs) == (0, 1000, 1000000, 0, 0)
+    assert rkc.lib().rkc_opts_default(None) == rkc.EINVAL
+    for code in (0, -1, -2, -3, -4, -5):
+        assert rkc.strerror(code) not in ("", "unknown error")
+    assert rkc.strerror(-99) == "unknown error"
+
+
+def _desc_arrays(m):
+    keep = {k: np.ascontiguousarray(m[k], np.int32 if k in ("reac", "prod") else np.float64)
+            for k in ["W", "nasa_low", "nasa_high", "T_mid", "reac", "prod", "A", "beta", "Ea"]}
+    return keep
+
+
+def _create(m, **over):
+    keep = _desc_arrays(m)
+    keep.update(over)
+    d = rkc.MechDesc(m["n_species"], m["n_reactions"],
+                     *[rkc._np_ptr(keep[k]) for k in ["W", "nasa_low", "nasa_high", "T_mid",
+                                                       "reac", "prod", "A", "beta", "Ea"]])
+    h = ct.c_void_p()
+    return rkc.lib().rkc_mech_create(ct.byref(d), ct.byref(h))
+
+
+def test_mech_create_rejects_bad_descriptions_without_a_device():
+    m = synth.config_mechanism("c1")
+    L = rkc.lib()
+    h = ct.c_void_p()
+    assert L.rkc_mech_create(None, ct.byref(h)) == rkc.EINVAL
+    bad = np.array(m["reac"], np.int32); bad[0, 0] = 9
+    assert _create(m, reac=bad) == rkc.EINVAL
+    bad = np.array(m["prod"], np.int32); bad[1, 1] = -2
+    assert _create(m, prod=bad) == rkc.EINVAL
+    w = np.array(m["W"]); w[0] = 0.0
+    assert _create(m, W=w) == rkc.EINVAL
+    a = np.array(m["A"]); a[2] = -1.0
+    assert _create(m, A=a) == rkc.EINVAL
+    e = np.array(m["Ea"]); e[3] = np.nan
+    assert _create(m, Ea=e) == rkc.EINVAL
+    d = rkc.MechDesc(1022, 0, *[None] * 9)
+    assert L.rkc_mech_create(ct.byref(d), ct.byref(h)) == rkc.ENOTSUP
+    d = rkc.MechDesc(0, 0, *[None] * 9)
+    assert L.rkc_mech_create(ct.byref(d), ct.byref(h)) == rkc.EINVAL
+
+
+def test_integrate_rejects_bad_arguments_without_a_device():
+    L = rkc.lib()
+    x = np.zeros(4)
+    assert L.rkc_integrate(None, 4, rkc._np_ptr(x), rkc._np_ptr(x), rkc._np_ptr(x), 1e-6, 1e-6,
+                           1e-10, None, None, None) == rkc.EINVAL
+    assert L.rkc_rhs(None, 4, None, None, None, None, None) == rkc.EINVAL
+    assert L.rkc_mech_destroy(None) == rkc.OK
+    assert L.rkc_mech_info(None, None, None, None, None) == rkc.EINVAL

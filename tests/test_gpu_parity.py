@@ -1,0 +1,177 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs, element by element, plus properties that hold at any size."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1309_2710_amd import synth
+from tests import parity as PT
+
+pytestmark = pytest.mark.gpu
+
+THREADS = min(16, os.cpu_count() or 1)
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def R():
+    from paper_1309_2710_amd import rkc
+    rkc.lib()
+    return rkc
+
+
+_MECHS = {}
+
+
+def mech(R, cfg):
+    if cfg not in _MECHS:
+        _MECHS[cfg] = (R.Mechanism(synth.config_mechanism(cfg)), O.Model(synth.config_mechanism(cfg)))
+    return _MECHS[cfg]
+
+
+RHS_CASES = [("c1", 8), ("c1", 16), ("c1", 32), ("c1", 64), ("c2", 8), ("c2", 16), ("c2", 64),
+             ("c3", 32), ("c3", 64), ("c4", 64)]
+
+
+@pytest.mark.parametrize("cfg,G", RHS_CASES)
+def test_rhs_parity(R, cfg, G):
+    _say("rhs", cfg, "G", G)
+    gm, om = mech(R, cfg)
+    st = synth.config_states(cfg, 333)
+    fg = R.rhs(gm, st["T"], st["P"], st["Y"], lanes_per_cell=G)
+    fo = om.rhs(st["T"], st["P"], st["Y"])
+    # species rates: relative to the cell's largest species rate (net production
+    # sums cancel); temperature rate: relative to itself
+    scale = np.abs(fo[:, 1:]).max(axis=1, keepdims=True)
+    eY = np.abs(fg[:, 1:] - fo[:, 1:]) / scale
+    eT = np.abs(fg[:, 0] - fo[:, 0]) / np.abs(fo[:, 0])
+    _say("max eY", eY.max(), "max eT", eT.max())
+    assert eY.max() <= 1e-12
+    assert eT.max() <= 1e-11
+
+
+def max_flips(cfg, n):
+    # long-horizon 111-species workload: ~1000 accepted steps per cell
+    return max(2, int(0.15 * n)) if cfg == "c4" else max(1, n // 100)
+
+
+INTEG_CASES = [("c1", 1024, O.RKC, 16), ("c1", 1024, O.RKC, 8), ("c1", 1024, O.RKC, 64),
+               ("c1", 1024, O.RKCK, 16), ("c2", 512, O.RKC, 16), ("c2", 512, O.RKCK, 16),
+               ("c3", 96, O.RKC, 64), ("c3", 96, O.RKC, 32), ("c4", 24, O.RKC, 64)]
+
+
+@pytest.mark.parametrize("cfg,n,method,G", INTEG_CASES)
+def test_integrate_parity(R, cfg, n, method, G):
+    _say("integrate", cfg, n, "method", method, "G", G)
+    gm, om = mech(R, cfg)
+    c = synth.CONFIGS[cfg]
+    st = synth.config_states(cfg, n)
+    Tg, Yg = st["T"].copy(), st["Y"].copy()
+    out = R.integrate(gm, Tg, st["P"], Yg, c["dt"], c["rtol"], c["atol"], method=method,
+                      lanes_per_cell=G, counters=True, stats=True)
+    To, Yo, co = om.integrate(st["T"], st["P"], st["Y"], c["dt"], c["rtol"], c["atol"],
+                              method=method, threads=THREADS)
+    assert (out["status"] == 0).all() and (co["status"] == 0).all()
+    rep = PT.check(Tg, Yg, out["counters"], To, Yo, co, c["rtol"], c["atol"],
+                   max_flips(cfg, n))
+    _say(rep, out["stats"])
+
+
+def test_schedules_and_grain_are_bitwise_invariant(R):
+    _say("schedule invariance c2")
+    gm, _ = mech(R, "c2")
+    c = synth.CONFIGS["c2"]
+    st = synth.config_states("c2", 700)
+    res = []
+    for kw in [dict(schedule=R.SCHED_PLAIN), dict(schedule=R.SCHED_PERSISTENT),
+               dict(schedule=R.SCHED_PERSISTENT, grid_blocks=3, block_groups=4),
+               dict(schedule=R.SCHED_PLAIN, block_groups=1)]:
+        T, Y = st["T"].copy(), st["Y"].copy()
+        out = R.integrate(gm, T, st["P"], Y, c["dt"], c["rtol"], c["atol"], lanes_per_cell=16,
+                          counters=True, **kw)
+        res.append((T, Y, out["counters"]))
+    for T, Y, cn in res[1:]:
+        assert np.array_equal(T, res[0][0]) and np.array_equal(Y, res[0][1])
+        assert np.array_equal(cn, res[0][2])
+
+
+def test_repeat_runs_bitwise_identical(R):
+    _say("repeat c3")
+    gm, _ = mech(R, "c3")
+    c = synth.CONFIGS["c3"]
+    st = synth.config_states("c3", 300)
+    outs = []
+    for _ in range(2):
+        T, Y = st["T"].copy(), st["Y"].copy()
+        R.integrate(gm, T, st["P"], Y, c["dt"], c["rtol"], c["atol"])
+        outs.append((T, Y))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_edge_cases(R):
+    _say("edge cases c1")
+    gm, om = mech(R, "c1")
+    c = synth.CONFIGS["c1"]
+    # empty batch
+    e = np.zeros(0)
+    out = R.integrate(gm, e.copy(), e.copy(), np.zeros((0, 9)), 1e-6)
+    assert out["rc"] == R.OK
+    # one cell and a ragged count
+    for n in (1, 65):
+        st = synth.config_states("c1", n)
+        T, Y = st["T"].copy(), st["Y"].copy()
+        R.integrate(gm, T, st["P"], Y, c["dt"], c["rtol"], c["atol"], lanes_per_cell=16)
+        To, Yo, _ = om.integrate(st["T"], st["P"], st["Y"], c["dt"], c["rtol"], c["atol"])
+        assert PT.rel_err(T, Y, To, Yo).max() <= PT.TOL
+    # bad inputs are flagged per cell; neighbours unaffected
+    st = synth.config_states("c1", 8)
+    T, P, Y = st["T"].copy(), st["P"].copy(), st["Y"].copy()
+    T[1] = -1.0; P[2] = 0.0; Y[3, 0] = np.nan; T[4] = np.inf
+    out = R.integrate(gm, T, P, Y, c["dt"], c["rtol"], c["atol"], lanes_per_cell=16)
+    assert out["rc"] == R.ECELLS
+    assert list(out["status"][1:5]) == [R.CELL_BADINPUT] * 4
+    assert T[1] == -1.0 and np.isinf(T[4])
+    To, Yo, co = om.integrate(st["T"][[0, 5, 6, 7]], st["P"][[0, 5, 6, 7]],
+                              st["Y"][[0, 5, 6, 7]], c["dt"], c["rtol"], c["atol"])
+    assert PT.rel_err(T[[0, 5, 6, 7]], Y[[0, 5, 6, 7]], To, Yo).max() <= PT.TOL
+    # step budget exhausted
+    st = synth.config_states("c1", 16)
+    T, Y = st["T"].copy(), st["Y"].copy()
+    out = R.integrate(gm, T, st["P"], Y, c["dt"], c["rtol"], c["atol"], max_steps=1,
+                      counters=True)
+    _, _, co = om.integrate(st["T"], st["P"], st["Y"], c["dt"], c["rtol"], c["atol"],
+                            max_steps=1)
+    assert (out["status"] == R.CELL_MAXSTEPS).all() and (co["status"] == O.MAXSTEPS).all()
+
+
+def test_full_size_c3_sampled(R):
+    """53sp/634rx at its full 131072 cells, device-resident, in the launch
+    configuration the benchmark times; the oracle checks a strided sample."""
+    import torch
+    _say("full c3 131072 cells")
+    gm, om = mech(R, "c3")
+    c = synth.CONFIGS["c3"]
+    st = synth.config_states("c3")
+    n = st["T"].shape[0]
+    T = torch.from_numpy(st["T"]).cuda()
+    P = torch.from_numpy(st["P"]).cuda()
+    Y = torch.from_numpy(st["Y"]).cuda()
+    out = R.integrate(gm, T, P, Y, c["dt"], c["rtol"], c["atol"], counters=True, stats=True)
+    torch.cuda.synchronize()
+    Tg, Yg = T.cpu().numpy(), Y.cpu().numpy()
+    cg = out["counters"].cpu().numpy()
+    _say("stats", out["stats"])
+    assert (out["status"].cpu().numpy() == 0).all()
+    assert np.abs(Yg.sum(1) - st["Y"].sum(1)).max() <= 1e-12
+    idx = np.arange(0, n, n // 64)[:64]
+    To, Yo, co = om.integrate(st["T"][idx], st["P"][idx], st["Y"][idx], c["dt"], c["rtol"],
+                              c["atol"], threads=THREADS)
+    rep = PT.check(Tg[idx], Yg[idx], cg[idx], To, Yo, co, c["rtol"], c["atol"], max_flips("c3", 64))
+    _say(rep)
