@@ -477,12 +477,17 @@ int orc_rkck_cell(const orc_model *md, double P, double *y, double dt, double rt
         int last = (h >= t_end - t);
         if (last) h = t_end - t;
         rkck_step(&c, y, h, k, z, y5, del);
+        /* largest |Delta_i / Delta_0,i|; any non-finite ratio makes the whole
+         * estimate non-finite (the step is then rejected) */
         double errmax = 0.0;
+        int nonfinite = 0;
         for (int i = 0; i < N; ++i) {
             double d0 = rtol * (fabs(y[i]) + fabs(k[i]) + 1e-30);
             double r = fabs(del[i] / d0);
-            if (!(r <= errmax)) errmax = r;   /* NaN propagates */
+            if (!isfinite(r)) nonfinite = 1;
+            else if (r > errmax) errmax = r;
         }
+        if (nonfinite) errmax = INFINITY;
         /* a trial step whose error is not finite is rejected with the largest shrink */
         if (errmax <= 1.0) {
             cnt->n_steps += 1;

@@ -5,11 +5,16 @@
 //   - state element k of y = {T, Y_1..Y_nS} lives on lane k % G, slot k / G;
 //   - reaction unit p (a forward/reverse pair, or one unpaired reaction) is
 //     evaluated by lane p % G, round p / G;
-//   - the net production sum (E:spec-rate) is a gather over a species-major
-//     table of (unit, nu'' - nu') entries, one species row per lane slot;
-//   - norms and mixture sums are XOR-butterfly reductions over the G lanes,
-//     so every lane of a group holds bitwise identical scalars and takes the
-//     same decisions.
+//   - the net production sum (E:spec-rate) is a load-balanced segmented
+//     gather: the species-major list of nonzero (species, unit) terms is cut
+//     into G equal runs, one per lane; each term is a 15-bit index into a
+//     signed copy of the net rates (+q at p, -q at p + RU*G, so no multiply or
+//     conversion is needed; |nu''-nu'| = 2 or 3 repeats the index), and each
+//     lane flushes its partial sum into a "piece" whenever the species
+//     changes; a species then adds its (one to four) pieces;
+//   - norms and mixture sums are reductions over the G lanes by DPP exchanges
+//     inside 16-lane rows and lane reads across rows, so every lane of a group
+//     holds bitwise identical scalars and takes the same decisions.
 // The integrator is written as a state machine in which every iteration of
 // the main loop performs exactly one source-term evaluation for every group
 // of the wave, whatever phase (power iteration, initial step, Chebyshev stage,
@@ -55,12 +60,19 @@ constexpr int UNIT_DOUBLES = 8;
 struct Tables {
     const double *units;     // [RU * G][8]
     const double *spec;      // [NFIELD][NK]
-    const int32_t *ent;      // [nnz] species-major: (unit << 8) | (dnu + 128)
-    const int32_t *row_ptr;  // [NK + 1] start of each state index's entries
+    const uint32_t *gather;  // [L2][G]: two 16-bit terms per word, see below
+    const int32_t *ps;       // [NK + 1] first piece of each state index
+    const int32_t *pbase;    // [G] first piece of each lane
 };
 
+// A gather term is 16 bits: bits 0..14 index the signed-rate array (RU*G*2
+// entries plus one slot that is always zero, used for padding); bit 15 marks
+// the last term of a species run inside the lane (flush the partial sum).
+constexpr uint32_t TERM_FLUSH = 0x8000u;
+constexpr uint32_t TERM_INDEX = 0x7fffu;
+
 struct Params {
-    int nS, N, NK, nU, RU, nnz;
+    int nS, N, NK, nU, RU, L2, NP;
     Tables tab;
     int n_cells;
     double *T;
@@ -85,36 +97,90 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+    const long long v = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_mov_dpp((int)v, CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(v >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ double readlane_f64(double x, int lane) {
+    const long long v = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)v, lane);
+    const int hi = __builtin_amdgcn_readlane((int)(v >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// DPP controls: quad_perm [1,0,3,2] (xor 1), [2,3,0,1] (xor 2), row_half_mirror
+// (lane i <-> 7-i within 8), row_mirror (lane i <-> 15-i within 16).  After the
+// four exchanges every lane of a 16-lane row holds the row sum, computed as
+// a + b in one lane and b + a in its partner (identical in IEEE arithmetic).
+constexpr int DPP_XOR1 = 0xB1, DPP_XOR2 = 0x4E, DPP_HALF_MIRROR = 0x141, DPP_MIRROR = 0x140;
+
+// Sum over the G lanes of a group (G = 8, 16, 32, 64); every lane of the
+// group receives the bitwise same value.
 template <int G>
 __device__ __forceinline__ double gsum(double x) {
-#pragma unroll
-    for (int m = G / 2; m >= 1; m >>= 1) x += __shfl_xor(x, m, G);
+    static_assert(G == 8 || G == 16 || G == 32 || G == 64, "group size");
+    x += dpp_f64<DPP_XOR1>(x);
+    x += dpp_f64<DPP_XOR2>(x);
+    x += dpp_f64<DPP_HALF_MIRROR>(x);
+    if constexpr (G >= 16) x += dpp_f64<DPP_MIRROR>(x);
+    if constexpr (G == 32) {
+        const double r0 = readlane_f64(x, 0), r1 = readlane_f64(x, 16);
+        const double r2 = readlane_f64(x, 32), r3 = readlane_f64(x, 48);
+        x = (__lane_id() < 32) ? r0 + r1 : r2 + r3;
+    } else if constexpr (G == 64) {
+        const double r0 = readlane_f64(x, 0), r1 = readlane_f64(x, 16);
+        const double r2 = readlane_f64(x, 32), r3 = readlane_f64(x, 48);
+        x = (r0 + r1) + (r2 + r3);
+    }
     return x;
 }
 
 template <int G>
 __device__ __forceinline__ void gsum2(double &a, double &b) {
-#pragma unroll
-    for (int m = G / 2; m >= 1; m >>= 1) {
-        double ta = __shfl_xor(a, m, G);
-        double tb = __shfl_xor(b, m, G);
-        a += ta;
-        b += tb;
-    }
+    a = gsum<G>(a);
+    b = gsum<G>(b);
 }
 
 template <int G>
 __device__ __forceinline__ double gmax(double x) {
-#pragma unroll
-    for (int m = G / 2; m >= 1; m >>= 1) x = fmax(x, __shfl_xor(x, m, G));
+    static_assert(G == 8 || G == 16 || G == 32 || G == 64, "group size");
+    x = fmax(x, dpp_f64<DPP_XOR1>(x));
+    x = fmax(x, dpp_f64<DPP_XOR2>(x));
+    x = fmax(x, dpp_f64<DPP_HALF_MIRROR>(x));
+    if constexpr (G >= 16) x = fmax(x, dpp_f64<DPP_MIRROR>(x));
+    if constexpr (G == 32) {
+        const double r0 = readlane_f64(x, 0), r1 = readlane_f64(x, 16);
+        const double r2 = readlane_f64(x, 32), r3 = readlane_f64(x, 48);
+        x = (__lane_id() < 32) ? fmax(r0, r1) : fmax(r2, r3);
+    } else if constexpr (G == 64) {
+        const double r0 = readlane_f64(x, 0), r1 = readlane_f64(x, 16);
+        const double r2 = readlane_f64(x, 32), r3 = readlane_f64(x, 48);
+        x = fmax(fmax(r0, r1), fmax(r2, r3));
+    }
     return x;
 }
 
+// Logical OR over the group's lanes (lanes of other groups are masked off).
 template <int G>
 __device__ __forceinline__ int gor(int x) {
-#pragma unroll
-    for (int m = G / 2; m >= 1; m >>= 1) x |= __shfl_xor(x, m, G);
-    return x;
+    const unsigned long long b = __ballot(x != 0);
+    if constexpr (G == 64) {
+        return b != 0ull;
+    } else {
+        const int base = (int)(__lane_id() / G) * G;
+        return ((b >> base) & ((1ull << G) - 1ull)) != 0ull;
+    }
+}
+
+// Value of lane 0 of the group.
+template <int G>
+__device__ __forceinline__ double gbcast0(double x) {
+    if constexpr (G == 64) return readlane_f64(x, 0);
+    else return __shfl(x, 0, G);
 }
 
 // Registers holding the reaction parameters of a lane's units (RUC > 0).
@@ -128,11 +194,13 @@ struct UnitRegs<0> {};
 
 struct GroupLds {
     const double *spec;
-    const int32_t *ent;
-    const int32_t *rowptr;
+    const uint32_t *gather;
+    const int32_t *ps;
+    const int32_t *pbase;
     const double *units;   // LDS copy (RUC == 0 only)
     double *C;             // [NK] concentrations, C[nS] == 1.0
-    double *Q;             // [RU * G] net rates of progress
+    double *Q;             // [2 RU G + 2]: +q, -q, then a zero slot
+    double *piece;         // [NP] partial sums of the gather
 };
 
 __device__ __forceinline__ double unpack_c(const double *C, uint32_t id, int s) {
@@ -144,8 +212,8 @@ __device__ __forceinline__ double unpack_c(const double *C, uint32_t id, int s) 
 template <int G, int NSL, int RUC>
 __device__ __forceinline__ void rhs_eval(const double (&z)[NSL], double P10, double (&fz)[NSL],
                                          const GroupLds &L, const UnitRegs<RUC> &ur,
-                                         int g, int NK, int N, int RU) {
-    const double T = __shfl(z[0], 0, G);
+                                         int g, int NK, int N, int RU, int L2) {
+    const double T = gbcast0<G>(z[0]);
     const double invT = 1.0 / T;
     const double lnT = log(T);
 
@@ -187,7 +255,9 @@ __device__ __forceinline__ void rhs_eval(const double (&z)[NSL], double P10, dou
             const uint32_t a = ur.idf[r], b = ur.idr[r];
             const double of = kf * unpack_c(L.C, a, 0) * unpack_c(L.C, a, 1) * unpack_c(L.C, a, 2);
             const double orv = kr * unpack_c(L.C, b, 0) * unpack_c(L.C, b, 1) * unpack_c(L.C, b, 2);
-            L.Q[r * G + g] = of - orv;
+            const double q = of - orv;
+            L.Q[r * G + g] = q;
+            L.Q[(RUC + r) * G + g] = -q;
         }
     } else {
         for (int r = 0; r < RU; ++r) {
@@ -200,23 +270,35 @@ __device__ __forceinline__ void rhs_eval(const double (&z)[NSL], double P10, dou
             const double kr = exp(u1.y + u2.x * lnT - u2.y * invT);
             const double of = kf * unpack_c(L.C, a, 0) * unpack_c(L.C, a, 1) * unpack_c(L.C, a, 2);
             const double orv = kr * unpack_c(L.C, b, 0) * unpack_c(L.C, b, 1) * unpack_c(L.C, b, 2);
-            L.Q[p] = of - orv;
+            const double q = of - orv;
+            L.Q[p] = q;
+            L.Q[p + RU * G] = -q;
         }
     }
     wave_sync();
 
     // Net production (E:spec-rate), species equations (E:mass) and the
     // enthalpy sum of the energy equation (E:energy).
+    {
+        double acc = 0.0;
+        int pid = L.pbase[g];
+        for (int e2 = 0; e2 < L2; ++e2) {
+            const uint32_t w = L.gather[e2 * G + g];
+            const uint32_t t0 = w & 0xffffu, t1 = w >> 16;
+            acc += L.Q[t0 & TERM_INDEX];
+            if (t0 & TERM_FLUSH) { L.piece[pid++] = acc; acc = 0.0; }
+            acc += L.Q[t1 & TERM_INDEX];
+            if (t1 & TERM_FLUSH) { L.piece[pid++] = acc; acc = 0.0; }
+        }
+    }
+    wave_sync();
     double hs = 0.0;
 #pragma unroll
     for (int s = 0; s < NSL; ++s) {
         const int k = s * G + g;
-        const int e0 = L.rowptr[k], e1 = L.rowptr[k + 1];
+        const int q0 = L.ps[k], q1 = L.ps[k + 1];
         double w = 0.0;
-        for (int e = e0; e < e1; ++e) {
-            const int en = L.ent[e];
-            w += (double)((en & 0xff) - 128) * L.Q[en >> 8];
-        }
+        for (int q = q0; q < q1; ++q) w += L.piece[q];
         fz[s] = L.spec[F_W * NK + k] * w / rho;
         hs += hRT[s] * w;
     }
@@ -228,12 +310,14 @@ __device__ __forceinline__ void rhs_eval(const double (&z)[NSL], double P10, dou
 
 // ---------------------------------------------------------------- staging
 
-__device__ __forceinline__ void stage_tables(const Params &p, double *spec_l, int32_t *ent_l,
-                                             int32_t *rowptr_l, double *units_l, int n_units_l) {
+__device__ __forceinline__ void stage_tables(const Params &p, int G, double *spec_l,
+                                             uint32_t *gather_l, int32_t *ps_l, int32_t *pbase_l,
+                                             double *units_l, int n_units_l) {
     const int tid = threadIdx.x, nt = blockDim.x;
     for (int i = tid; i < NFIELD * p.NK; i += nt) spec_l[i] = p.tab.spec[i];
-    for (int i = tid; i < p.nnz; i += nt) ent_l[i] = p.tab.ent[i];
-    for (int i = tid; i <= p.NK; i += nt) rowptr_l[i] = p.tab.row_ptr[i];
+    for (int i = tid; i < p.L2 * G; i += nt) gather_l[i] = p.tab.gather[i];
+    for (int i = tid; i <= p.NK; i += nt) ps_l[i] = p.tab.ps[i];
+    for (int i = tid; i < G; i += nt) pbase_l[i] = p.tab.pbase[i];
     for (int i = tid; i < n_units_l * UNIT_DOUBLES; i += nt) units_l[i] = p.tab.units[i];
 }
 
@@ -255,38 +339,64 @@ __device__ __forceinline__ void load_unit_regs(const Params &p, UnitRegs<RUC> &u
 // Bytes of per-group control state kept in LDS by the integrator kernels.
 constexpr int STATE_BYTES = 256;
 
+// Doubles of per-group LDS: concentrations, signed net rates (+ zero slot,
+// padded to even), gather pieces (padded to even).
+__host__ __device__ inline size_t group_doubles(int NK, int RU, int G, int NP) {
+    return (size_t)NK + (size_t)2 * RU * G + 2 + (size_t)((NP + 1) & ~1);
+}
+
 // Bytes of dynamic LDS for a workgroup of `groups` groups.
-__host__ __device__ inline size_t lds_bytes(int NK, int RU, int G, int nnz, int groups,
+__host__ __device__ inline size_t lds_bytes(int NK, int RU, int G, int L2, int NP, int groups,
                                             bool units_in_lds) {
     size_t b = (size_t)NFIELD * NK * 8;
     if (units_in_lds) b += (size_t)RU * G * UNIT_DOUBLES * 8;
-    b += (size_t)groups * ((size_t)NK + (size_t)RU * G) * 8;
+    b += (size_t)groups * group_doubles(NK, RU, G, NP) * 8;
     b += (size_t)groups * STATE_BYTES;
-    b += (size_t)nnz * 4 + ((size_t)NK + 1) * 4;
+    b += (size_t)L2 * G * 4 + ((size_t)NK + 1) * 4 + (size_t)G * 4;
     return b;
 }
 
 struct LdsPtrs {
     double *spec, *units;
-    int32_t *ent, *rowptr;
+    uint32_t *gather;
+    int32_t *ps, *pbase;
     double *groups;
     unsigned char *states;
 };
 
-__device__ __forceinline__ LdsPtrs carve(unsigned char *base, int NK, int RU, int G, int nnz,
-                                         int groups, bool units_in_lds) {
+__device__ __forceinline__ LdsPtrs carve(unsigned char *base, int NK, int RU, int G, int L2,
+                                         int NP, int groups, bool units_in_lds) {
     LdsPtrs l;
     size_t off = 0;
     l.spec = reinterpret_cast<double *>(base + off); off += (size_t)NFIELD * NK * 8;
     l.units = reinterpret_cast<double *>(base + off);
     if (units_in_lds) off += (size_t)RU * G * UNIT_DOUBLES * 8;
     l.groups = reinterpret_cast<double *>(base + off);
-    off += (size_t)groups * ((size_t)NK + (size_t)RU * G) * 8;
+    off += (size_t)groups * group_doubles(NK, RU, G, NP) * 8;
     l.states = base + off;
     off += (size_t)groups * STATE_BYTES;
-    l.ent = reinterpret_cast<int32_t *>(base + off); off += (size_t)nnz * 4;
-    l.rowptr = reinterpret_cast<int32_t *>(base + off);
+    l.gather = reinterpret_cast<uint32_t *>(base + off); off += (size_t)L2 * G * 4;
+    l.ps = reinterpret_cast<int32_t *>(base + off); off += ((size_t)NK + 1) * 4;
+    l.pbase = reinterpret_cast<int32_t *>(base + off);
     return l;
+}
+
+// Per-group LDS views and their one-time initialisation (absent-slot
+// concentration 1.0, the zero slot of the signed rates).
+__device__ __forceinline__ GroupLds group_view(const LdsPtrs &lp, const Params &p, int G,
+                                               int gib) {
+    GroupLds L;
+    L.spec = lp.spec; L.gather = lp.gather; L.ps = lp.ps; L.pbase = lp.pbase;
+    L.units = lp.units;
+    L.C = lp.groups + (size_t)gib * group_doubles(p.NK, p.RU, G, p.NP);
+    L.Q = L.C + p.NK;
+    L.piece = L.Q + 2 * p.RU * G + 2;
+    return L;
+}
+
+__device__ __forceinline__ void group_init(const GroupLds &L, const Params &p, int G, int g) {
+    for (int k = g; k < p.NK; k += G) L.C[k] = (k == p.nS) ? 1.0 : 0.0;
+    if (g == 0) { L.Q[2 * p.RU * G] = 0.0; L.Q[2 * p.RU * G + 1] = 0.0; }
 }
 
 // ------------------------------------------------------- source-term kernel
@@ -297,13 +407,10 @@ __global__ __launch_bounds__(512) void rhs_kernel(Params p) {
     const int groups = blockDim.x / G;
     const int gib = threadIdx.x / G;
     const int g = threadIdx.x % G;
-    LdsPtrs lp = carve(lds_raw, p.NK, p.RU, G, p.nnz, groups, RUC == 0);
-    stage_tables(p, lp.spec, lp.ent, lp.rowptr, lp.units, RUC == 0 ? p.RU * G : 0);
-    GroupLds L;
-    L.spec = lp.spec; L.ent = lp.ent; L.rowptr = lp.rowptr; L.units = lp.units;
-    L.C = lp.groups + (size_t)gib * (p.NK + p.RU * G);
-    L.Q = L.C + p.NK;
-    for (int k = g; k < p.NK; k += G) L.C[k] = (k == p.nS) ? 1.0 : 0.0;
+    LdsPtrs lp = carve(lds_raw, p.NK, p.RU, G, p.L2, p.NP, groups, RUC == 0);
+    stage_tables(p, G, lp.spec, lp.gather, lp.ps, lp.pbase, lp.units, RUC == 0 ? p.RU * G : 0);
+    GroupLds L = group_view(lp, p, G, gib);
+    group_init(L, p, G, g);
     __syncthreads();
     UnitRegs<RUC> ur;
     load_unit_regs<RUC>(p, ur, g, G);
@@ -323,7 +430,7 @@ __global__ __launch_bounds__(512) void rhs_kernel(Params p) {
     }
     if (!active) z[0] = (g == 0) ? 1000.0 : z[0];
     const double P10 = active ? p.P[cell] * 10.0 : 1e6;
-    rhs_eval<G, NSL, RUC>(z, P10, fz, L, ur, g, p.NK, p.N, p.RU);
+    rhs_eval<G, NSL, RUC>(z, P10, fz, L, ur, g, p.NK, p.N, p.RU, p.L2);
     if (active) {
 #pragma unroll
         for (int s = 0; s < NSL; ++s) {

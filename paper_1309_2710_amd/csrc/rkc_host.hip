@@ -18,11 +18,14 @@ namespace {
 constexpr double R_J = 8.31446261815324;   // J/(mol K)
 constexpr double LNA_ZERO = -1e300;        // ln A of a reaction whose rate is identically 0
 
+// Device tables that depend on the lane-group shape: the species table is
+// laid out with stride NK, the gather is balanced over G lanes.
 struct NkTables {
-    int NK = 0;
+    int G = 0, NK = 0, RU = 0, L2 = 0, NP = 0;
     double *spec = nullptr;
-    int32_t *ent = nullptr;
-    int32_t *rowptr = nullptr;
+    uint32_t *gather = nullptr;
+    int32_t *ps = nullptr;
+    int32_t *pbase = nullptr;
 };
 
 }  // namespace
@@ -75,9 +78,64 @@ double ln_a(double A) { return A > 0.0 ? std::log(A) : LNA_ZERO; }
         if ((expr) != hipSuccess) return RKC_EDEVICE;         \
     } while (0)
 
-int ensure_nk(rkc_mech *m, int NK, NkTables **out) {
+// Balanced segmented gather for the net production sum (E:spec-rate): the
+// species-major list of signed-rate indices is cut into G equal runs.
+struct GatherPlan {
+    int L2 = 0, NP = 0;
+    std::vector<uint32_t> words;   // [L2][G]
+    std::vector<int32_t> ps;       // [NK + 1]
+    std::vector<int32_t> pbase;    // [G]
+};
+
+int plan_gather(const rkc_mech *m, int G, int NK, int RU, GatherPlan *gp) {
+    const int RUG = RU * G;
+    const uint32_t zero_slot = (uint32_t)(2 * RUG);
+    if (2 * RUG + 1 > (int)rkcdev::TERM_INDEX) return RKC_ENOTSUP;
+    std::vector<uint32_t> idx;   // signed-rate index per term
+    std::vector<int> spk;        // state index of each term
+    for (int i = 0; i < m->nS; ++i)
+        for (const auto &pr : m->rows[i]) {
+            const uint32_t id = pr.second > 0 ? (uint32_t)pr.first : (uint32_t)(pr.first + RUG);
+            for (int r = 0; r < std::abs(pr.second); ++r) {
+                idx.push_back(id);
+                spk.push_back(i + 1);
+            }
+        }
+    const int M = (int)idx.size();
+    const int L = std::max(1, (M + G - 1) / G);
+    gp->L2 = (L + 1) / 2;
+    gp->words.assign((size_t)gp->L2 * G, 0u);
+    gp->pbase.assign(G, 0);
+    std::vector<int> piece_sp;   // state index of each piece, in piece order
+    for (int g = 0; g < G; ++g) {
+        gp->pbase[g] = (int)piece_sp.size();
+        const int e0 = std::min(M, g * L), e1 = std::min(M, (g + 1) * L);
+        for (int e = 0; e < 2 * gp->L2; ++e) {
+            uint32_t term = zero_slot;
+            const int t = e0 + e;
+            if (t < e1) {
+                term = idx[t];
+                if (t + 1 == e1 || spk[t + 1] != spk[t]) {
+                    term |= rkcdev::TERM_FLUSH;
+                    piece_sp.push_back(spk[t]);
+                }
+            }
+            gp->words[(size_t)(e / 2) * G + g] |= term << (16 * (e % 2));
+        }
+    }
+    gp->NP = (int)piece_sp.size();
+    gp->ps.assign(NK + 1, 0);
+    int q = 0;
+    for (int k = 0; k <= NK; ++k) {
+        while (q < gp->NP && piece_sp[q] < k) ++q;
+        gp->ps[k] = q;
+    }
+    return RKC_OK;
+}
+
+int ensure_tables(rkc_mech *m, int G, int NK, int RU, NkTables **out) {
     for (auto &t : m->nk)
-        if (t.NK == NK) { *out = &t; return RKC_OK; }
+        if (t.NK == NK && t.G == G) { *out = &t; return RKC_OK; }
     const int nS = m->nS;
     std::vector<double> spec((size_t)NFIELD * NK, 0.0);
     for (int i = 0; i < nS; ++i) {
@@ -99,26 +157,26 @@ int ensure_nk(rkc_mech *m, int NK, NkTables **out) {
             put(ho[r] + 5, a[r][5]);
         }
     }
-    // species-major CSR over state indices: row k = i + 1 lists species i's entries
-    std::vector<int32_t> ent, rowptr(NK + 1, 0);
-    ent.reserve(std::max(1, m->nnz));
-    for (int k = 0; k < NK; ++k) {
-        rowptr[k] = (int32_t)ent.size();
-        if (k >= 1 && k <= nS)
-            for (const auto &pr : m->rows[k - 1]) ent.push_back((pr.first << 8) | (pr.second + 128));
-    }
-    rowptr[NK] = (int32_t)ent.size();
-    if (ent.empty()) ent.push_back(0);
+    GatherPlan gp;
+    int rc = plan_gather(m, G, NK, RU, &gp);
+    if (rc) return rc;
     NkTables t;
+    t.G = G;
     t.NK = NK;
+    t.RU = RU;
+    t.L2 = gp.L2;
+    t.NP = gp.NP;
     if (hipMalloc(&t.spec, spec.size() * 8) != hipSuccess) return RKC_ENOMEM;
-    if (hipMalloc(&t.ent, ent.size() * 4) != hipSuccess) { (void)hipFree(t.spec); return RKC_ENOMEM; }
-    if (hipMalloc(&t.rowptr, rowptr.size() * 4) != hipSuccess) {
-        (void)hipFree(t.spec); (void)hipFree(t.ent); return RKC_ENOMEM;
+    if (hipMalloc(&t.gather, gp.words.size() * 4) != hipSuccess ||
+        hipMalloc(&t.ps, gp.ps.size() * 4) != hipSuccess ||
+        hipMalloc(&t.pbase, gp.pbase.size() * 4) != hipSuccess) {
+        (void)hipFree(t.spec); (void)hipFree(t.gather); (void)hipFree(t.ps);
+        return RKC_ENOMEM;
     }
     HIP_OK(hipMemcpy(t.spec, spec.data(), spec.size() * 8, hipMemcpyHostToDevice));
-    HIP_OK(hipMemcpy(t.ent, ent.data(), ent.size() * 4, hipMemcpyHostToDevice));
-    HIP_OK(hipMemcpy(t.rowptr, rowptr.data(), rowptr.size() * 4, hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(t.gather, gp.words.data(), gp.words.size() * 4, hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(t.ps, gp.ps.data(), gp.ps.size() * 4, hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(t.pbase, gp.pbase.data(), gp.pbase.size() * 4, hipMemcpyHostToDevice));
     m->nk.push_back(t);
     *out = &m->nk.back();
     return RKC_OK;
@@ -187,7 +245,7 @@ int plan_launch(const rkc_mech *m, const Choice &ch, const void *kernel, size_t 
     int gpb = o.block_groups > 0 ? o.block_groups : std::max(1, 256 / G);
     if (gpb * G > 512) gpb = 512 / G;
     auto need = [&](int groups) {
-        return rkcdev::lds_bytes(NK, ch.RU, G, std::max(1, m->nnz), groups, ch.v.RUC == 0);
+        return rkcdev::lds_bytes(NK, ch.RU, G, nk->L2, nk->NP, groups, ch.v.RUC == 0);
     };
     while (gpb > 1 && need(gpb) > m->max_lds) gpb = (gpb + 1) / 2;
     if (need(gpb) > m->max_lds) return RKC_ENOTSUP;
@@ -226,11 +284,13 @@ void fill_params(const rkc_mech *m, const Choice &ch, const NkTables *nk, rkcdev
     p->NK = nk->NK;
     p->nU = m->nU;
     p->RU = ch.RU;
-    p->nnz = std::max(1, m->nnz);
+    p->L2 = nk->L2;
+    p->NP = nk->NP;
     p->tab.units = m->units_d;
     p->tab.spec = nk->spec;
-    p->tab.ent = nk->ent;
-    p->tab.row_ptr = nk->rowptr;
+    p->tab.gather = nk->gather;
+    p->tab.ps = nk->ps;
+    p->tab.pbase = nk->pbase;
     p->agg = m->agg_d;
     p->queue = m->queue_d;
 }
@@ -269,8 +329,9 @@ int rkc_mech_destroy(rkc_mech *m) {
     if (m->units_d) (void)hipFree(m->units_d);
     for (auto &t : m->nk) {
         (void)hipFree(t.spec);
-        (void)hipFree(t.ent);
-        (void)hipFree(t.rowptr);
+        (void)hipFree(t.gather);
+        (void)hipFree(t.ps);
+        (void)hipFree(t.pbase);
     }
     if (m->agg_d) (void)hipFree(m->agg_d);
     if (m->queue_d) (void)hipFree(m->queue_d);
@@ -414,7 +475,7 @@ int rkc_rhs(const rkc_mech *mc, size_t n, const double *T, const double *P, cons
     int rc = choose_variant(m, o.lanes_per_cell, &ch);
     if (rc) return rc;
     NkTables *nk = nullptr;
-    rc = ensure_nk(m, ch.v.NSL * ch.v.G, &nk);
+    rc = ensure_tables(m, ch.v.G, ch.v.NSL * ch.v.G, ch.RU, &nk);
     if (rc) return rc;
     hipStream_t st = (hipStream_t)o.stream;
     const double *Td = T, *Pd = P, *Yd = Y;
@@ -478,7 +539,7 @@ int rkc_integrate(const rkc_mech *mc, size_t n, double *T, const double *P, doub
     int rc = choose_variant(m, o.lanes_per_cell, &ch);
     if (rc) return rc;
     NkTables *nk = nullptr;
-    rc = ensure_nk(m, ch.v.NSL * ch.v.G, &nk);
+    rc = ensure_tables(m, ch.v.G, ch.v.NSL * ch.v.G, ch.RU, &nk);
     if (rc) return rc;
     const void *kernel = o.method == RKC_METHOD_RKC ? ch.v.k_rkc : ch.v.k_rkck;
     Launch L;

@@ -150,13 +150,11 @@ __device__ __forceinline__ double rms_norm(const double (&d)[NSL], const double 
     const int groups = blockDim.x / G;                                                       \
     const int gib = threadIdx.x / G;                                                         \
     const int g = threadIdx.x % G;                                                           \
-    LdsPtrs lp = carve(lds_raw, p.NK, p.RU, G, p.nnz, groups, RUC == 0);                     \
-    stage_tables(p, lp.spec, lp.ent, lp.rowptr, lp.units, RUC == 0 ? p.RU * G : 0);          \
-    GroupLds L;                                                                              \
-    L.spec = lp.spec; L.ent = lp.ent; L.rowptr = lp.rowptr; L.units = lp.units;              \
-    L.C = lp.groups + (size_t)gib * (p.NK + p.RU * G);                                       \
-    L.Q = L.C + p.NK;                                                                        \
-    for (int k = g; k < p.NK; k += G) L.C[k] = (k == p.nS) ? 1.0 : 0.0;                      \
+    LdsPtrs lp = carve(lds_raw, p.NK, p.RU, G, p.L2, p.NP, groups, RUC == 0);                \
+    stage_tables(p, G, lp.spec, lp.gather, lp.ps, lp.pbase, lp.units,                        \
+                 RUC == 0 ? p.RU * G : 0);                                                   \
+    GroupLds L = group_view(lp, p, G, gib);                                                  \
+    group_init(L, p, G, g);                                                                  \
     __syncthreads();                                                                         \
     UnitRegs<RUC> ur;                                                                        \
     load_unit_regs<RUC>(p, ur, g, G);                                                        \
@@ -224,7 +222,7 @@ __global__ __launch_bounds__(512) void rkc_kernel(Params p) {
     acquire(blockIdx.x * groups + gib);
 
     for (;;) {
-        rhs_eval<G, NSL, RUC>(z, S.P10, fz, L, ur, g, p.NK, N, p.RU);
+        rhs_eval<G, NSL, RUC>(z, S.P10, fz, L, ur, g, p.NK, N, p.RU, p.L2);
         if (S.cell >= 0) {
             Counts c = S.c;
             c.n_rhs += 1;
@@ -545,7 +543,7 @@ __global__ __launch_bounds__(512) void rkck_kernel(Params p) {
     acquire(blockIdx.x * groups + gib);
 
     for (;;) {
-        rhs_eval<G, NSL, RUC>(z, S.P10, fz, L, ur, g, p.NK, N, p.RU);
+        rhs_eval<G, NSL, RUC>(z, S.P10, fz, L, ur, g, p.NK, N, p.RU, p.L2);
         if (S.cell >= 0) {
             Counts c = S.c;
             c.n_rhs += 1;

@@ -74,6 +74,13 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("librkc.so not built: run __graft_entry__.build() "
                                "or python paper_1309_2710_amd/build.py")
+        # torch ships its own HIP runtime under the same soname; loading it first
+        # makes it the single runtime of the process, shared with this library
+        # (device pointers and streams from torch are then valid here).
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ct.CDLL(LIB_PATH)
         L.rkc_opts_default.argtypes = [ct.POINTER(Opts)]
         L.rkc_mech_create.argtypes = [ct.POINTER(MechDesc), ct.POINTER(ct.c_void_p)]

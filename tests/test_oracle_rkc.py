@@ -365,3 +365,16 @@ def test_status_codes():
     assert (c3["status"] == O.MAXSTEPS).all()
     _, _, c4 = M.integrate(st["T"], st["P"], st["Y"], 1e-6, s_max=2)
     assert (c4["status"] != O.OK).any()
+
+
+def test_rkck_never_accepts_a_nonfinite_trial_step():
+    """A too-large first trial step on a stiff mechanism overflows some stage
+    components; the error test must reject it (not accept a NaN state)."""
+    m = synth.config_mechanism("c3")
+    M = O.Model(m)
+    st = synth.config_states("c3", 64)
+    T, Y, cnt = M.integrate(st["T"], st["P"], st["Y"], 1e-8, 1e-10, 1e-10, method=O.RKCK,
+                            threads=8)
+    assert (cnt["status"] == O.OK).all()
+    assert np.isfinite(T).all() and np.isfinite(Y).all()
+    assert (cnt["n_reject"][[20, 54]] > 0).all()
