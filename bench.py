@@ -73,6 +73,7 @@ def main():
     ap.add_argument("--config", default="c3")
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--schedule", type=int, default=0)
+    ap.add_argument("--params", type=int, default=0, help="0 auto, 1 registers, 2 LDS")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     args = ap.parse_args()
@@ -98,7 +99,8 @@ def main():
     Y0 = torch.from_numpy(st["Y"]).to(dev)
     T = T0.clone()
     Y = Y0.clone()
-    kw = dict(lanes_per_cell=args.lanes, schedule=args.schedule, status=False)
+    kw = dict(lanes_per_cell=args.lanes, schedule=args.schedule, status=False,
+              param_placement=args.params)
 
     # Warm-up and work census: the K timed steps are replayed once untimed with
     # statistics (results are bitwise deterministic, so the timed run performs

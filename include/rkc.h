@@ -64,6 +64,12 @@ extern "C" {
 #define RKC_SCHED_PLAIN       1  /* one lane group per cell, grid covers all cells */
 #define RKC_SCHED_PERSISTENT  2  /* resident grid; groups pull cells from a device queue */
 
+/* ---- placement of reaction parameters (never changes results) --------- */
+#define RKC_PARAMS_AUTO       0  /* LDS (the measured faster placement) */
+#define RKC_PARAMS_REGISTERS  1  /* registers, when a variant for the mechanism's size
+                                    is compiled (else LDS) */
+#define RKC_PARAMS_LDS        2
+
 /* Number of int32 per cell in opts->cell_counters. */
 #define RKC_NCOUNTERS 8
 /* Column order of opts->cell_counters rows. */
@@ -112,6 +118,7 @@ typedef struct {
     int32_t device_ptrs;     /* 0: host arrays; 1: device arrays (see top) */
     void   *stream;          /* hipStream_t; NULL = the null stream */
     int32_t *cell_counters;  /* optional [n_cells][RKC_NCOUNTERS] per-cell counters */
+    int32_t param_placement; /* RKC_PARAMS_AUTO */
 } rkc_opts;
 
 /* Aggregate statistics of one call. */

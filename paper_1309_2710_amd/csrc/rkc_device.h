@@ -5,13 +5,15 @@
 //   - state element k of y = {T, Y_1..Y_nS} lives on lane k % G, slot k / G;
 //   - reaction unit p (a forward/reverse pair, or one unpaired reaction) is
 //     evaluated by lane p % G, round p / G;
-//   - the net production sum (E:spec-rate) is a load-balanced segmented
-//     gather: the species-major list of nonzero (species, unit) terms is cut
-//     into G equal runs, one per lane; each term is a 15-bit index into a
-//     signed copy of the net rates (+q at p, -q at p + RU*G, so no multiply or
-//     conversion is needed; |nu''-nu'| = 2 or 3 repeats the index), and each
-//     lane flushes its partial sum into a "piece" whenever the species
-//     changes; a species then adds its (one to four) pieces;
+//   - the net production sum (E:spec-rate) is a load-balanced gather: each
+//     species' nonzero terms, split by the sign of nu'' - nu', are cut into
+//     chunks of at most SEGL terms; chunk c goes to lane c % G, segment c / G,
+//     and every lane runs the same NSEG segments of SEGL terms (short chunks
+//     padded with a zero term), so the loop has no divergence and a
+//     segment's loads issue back to back.  A term is the 16-bit byte offset
+//     of a unit's net rate q (|nu''-nu'| = 2 or 3 repeats the term).  Each
+//     segment's sum is a "piece"; a species adds its positive pieces and
+//     subtracts its negative ones, both consecutive;
 //   - norms and mixture sums are reductions over the G lanes by DPP exchanges
 //     inside 16-lane rows and lane reads across rows, so every lane of a group
 //     holds bitwise identical scalars and takes the same decisions.
@@ -60,19 +62,17 @@ constexpr int UNIT_DOUBLES = 8;
 struct Tables {
     const double *units;     // [RU * G][8]
     const double *spec;      // [NFIELD][NK]
-    const uint32_t *gather;  // [L2][G]: two 16-bit terms per word, see below
-    const int32_t *ps;       // [NK + 1] first piece of each state index
-    const int32_t *pbase;    // [G] first piece of each lane
+    const uint32_t *gather;  // [NSEG * SEGL / 2][G]: two 16-bit terms per word
+    const int32_t *ps;       // [2 NK + 1]: pieces of state index k are
+                             // [ps[2k], ps[2k+1]) positive, [ps[2k+1], ps[2k+2]) negative
 };
 
-// A gather term is 16 bits: bits 0..14 index the signed-rate array (RU*G*2
-// entries plus one slot that is always zero, used for padding); bit 15 marks
-// the last term of a species run inside the lane (flush the partial sum).
-constexpr uint32_t TERM_FLUSH = 0x8000u;
-constexpr uint32_t TERM_INDEX = 0x7fffu;
+// A gather term is the byte offset, inside the group's rate array, of a unit's
+// net rate q (RU G entries plus one slot that is always zero, for padding).
+constexpr uint32_t TERM_MAX_BYTES = 0xffffu;
 
 struct Params {
-    int nS, N, NK, nU, RU, L2, NP;
+    int nS, N, NK, nU, RU, NSEG, SEGL;
     Tables tab;
     int n_cells;
     double *T;
@@ -196,32 +196,75 @@ struct GroupLds {
     const double *spec;
     const uint32_t *gather;
     const int32_t *ps;
-    const int32_t *pbase;
     const double *units;   // LDS copy (RUC == 0 only)
     double *C;             // [NK] concentrations, C[nS] == 1.0
-    double *Q;             // [2 RU G + 2]: +q, -q, then a zero slot
-    double *piece;         // [NP] partial sums of the gather
+    double *Q;             // [RU G + 2]: net rates q, then a zero slot
+    double *piece;         // [NSEG * G] partial sums of the gather
 };
 
 __device__ __forceinline__ double unpack_c(const double *C, uint32_t id, int s) {
     return C[(id >> (10 * s)) & 1023u];
 }
 
+// Natural logarithm of a positive finite double (NaN otherwise).  Argument
+// reduction x = m 2^e with m in [sqrt(1/2), sqrt(2)), then
+// log x = e ln2 + 2 atanh(s), s = (m - 1)/(m + 1), |s| <= 0.1716, with the odd
+// Taylor series of atanh through s^23 (truncation below 2^-60 relative); ln 2
+// is split into a head with trailing zero bits and a tail (Cody & Waite) so
+// e * ln2_hi is exact.  Within one ulp of the correctly rounded value.
+__device__ __forceinline__ double log_pos(double x) {
+    int e;
+    double m = frexp(x, &e);
+    const bool lo = m < 0.70710678118654752440;
+    m = lo ? 2.0 * m : m;
+    e = lo ? e - 1 : e;
+    const double s = (m - 1.0) / (m + 1.0);
+    const double s2 = s * s;
+    double q = 1.0 / 23.0;
+    q = q * s2 + 1.0 / 21.0;
+    q = q * s2 + 1.0 / 19.0;
+    q = q * s2 + 1.0 / 17.0;
+    q = q * s2 + 1.0 / 15.0;
+    q = q * s2 + 1.0 / 13.0;
+    q = q * s2 + 1.0 / 11.0;
+    q = q * s2 + 1.0 / 9.0;
+    q = q * s2 + 1.0 / 7.0;
+    q = q * s2 + 1.0 / 5.0;
+    q = q * s2 + 1.0 / 3.0;
+    const double ln2_hi = 0x1.62e42fee00000p-1, ln2_lo = 0x1.a39ef35793c76p-33;
+    const double de = (double)e;
+    const double r = (de * ln2_hi + 2.0 * s) + (de * ln2_lo + (2.0 * s * s2) * q);
+    return (x > 0.0 && x <= 0x1.fffffffffffffp+1023) ? r : __builtin_nan("");
+}
+
+// A zero the compiler cannot see through.  Adding it to loop-invariant table
+// indices keeps the (cheap) address arithmetic inside the integration loop
+// instead of pinning one register per address for the lifetime of the wave.
+__device__ __forceinline__ uint32_t opaque_zero() {
+    uint32_t z;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(z));
+    return z;
+}
+
 // Source term of E:mass and E:energy for the group's cell at state z.
 // z/fz hold this lane's NSL elements (index k = s * G + g).
 template <int G, int NSL, int RUC>
-__device__ __forceinline__ void rhs_eval(const double (&z)[NSL], double P10, double (&fz)[NSL],
-                                         const GroupLds &L, const UnitRegs<RUC> &ur,
-                                         int g, int NK, int N, int RU, int L2) {
+__device__ __forceinline__ void rhs_eval(const double (&z)[NSL], double P10, double invP10,
+                                         double (&fz)[NSL], const GroupLds &L,
+                                         const UnitRegs<RUC> &ur, int g, int N, int RU, int NSEG,
+                                         int SEGL) {
+    constexpr int NK = NSL * G;
+    const uint32_t oz = opaque_zero();
+    const int go = g + (int)oz;
     const double T = gbcast0<G>(z[0]);
     const double invT = 1.0 / T;
-    const double lnT = log(T);
+    const double lnT = log_pos(T);
 
     double sYW = 0.0, sYcp = 0.0;
     double hRT[NSL], invW[NSL];
 #pragma unroll
     for (int s = 0; s < NSL; ++s) {
-        const int k = s * G + g;
+        const int k = s * G + go;
         const double Y = (k == 0) ? 0.0 : z[s];
         invW[s] = L.spec[F_INVW * NK + k];
         const bool hi = T >= L.spec[F_TMID * NK + k];
@@ -235,30 +278,39 @@ __device__ __forceinline__ void rhs_eval(const double (&z)[NSL], double P10, dou
         sYcp += YW * cpR;
     }
     gsum2<G>(sYW, sYcp);
-    const double rho = P10 / (R_ERG * T * sYW);
+    const double RTW = R_ERG * T * sYW;
+    const double rho = P10 / RTW;          // ideal gas, g/cm^3
+    const double inv_rho = RTW * invP10;
+
+    // The C, Q and piece arrays never overlap; telling the compiler so lets it
+    // issue the loads of one unit or segment before the stores of the last.
+    double *__restrict__ C = L.C;
+    double *__restrict__ Q = L.Q;
+    double *__restrict__ piece = L.piece;
 
     wave_sync();   // previous evaluation's readers of C are done
 #pragma unroll
     for (int s = 0; s < NSL; ++s) {
-        const int k = s * G + g;
-        if (k >= 1 && k < N) L.C[k - 1] = rho * z[s] * invW[s];
+        const int k = s * G + go;
+        if (k >= 1 && k < N) C[k - 1] = rho * z[s] * invW[s];
     }
     wave_sync();
 
     // Rates of progress (E:rxn-rate) with Arrhenius coefficients (E:rxn-const),
     // net of each forward/reverse pair.
     if constexpr (RUC > 0) {
+        double q[RUC];
 #pragma unroll
         for (int r = 0; r < RUC; ++r) {
             const double kf = exp(ur.lnAf[r] + ur.bf[r] * lnT - ur.tf[r] * invT);
             const double kr = exp(ur.lnAr[r] + ur.br[r] * lnT - ur.tr[r] * invT);
-            const uint32_t a = ur.idf[r], b = ur.idr[r];
-            const double of = kf * unpack_c(L.C, a, 0) * unpack_c(L.C, a, 1) * unpack_c(L.C, a, 2);
-            const double orv = kr * unpack_c(L.C, b, 0) * unpack_c(L.C, b, 1) * unpack_c(L.C, b, 2);
-            const double q = of - orv;
-            L.Q[r * G + g] = q;
-            L.Q[(RUC + r) * G + g] = -q;
+            const uint32_t a = ur.idf[r] + oz, b = ur.idr[r] + oz;
+            const double of = kf * unpack_c(C, a, 0) * unpack_c(C, a, 1) * unpack_c(C, a, 2);
+            const double orv = kr * unpack_c(C, b, 0) * unpack_c(C, b, 1) * unpack_c(C, b, 2);
+            q[r] = of - orv;
         }
+#pragma unroll
+        for (int r = 0; r < RUC; ++r) Q[r * G + go] = q[r];
     } else {
         for (int r = 0; r < RU; ++r) {
             const int p = r * G + g;
@@ -268,11 +320,9 @@ __device__ __forceinline__ void rhs_eval(const double (&z)[NSL], double P10, dou
             const uint32_t a = (uint32_t)bits, b = (uint32_t)(bits >> 32);
             const double kf = exp(u0.x + u0.y * lnT - u1.x * invT);
             const double kr = exp(u1.y + u2.x * lnT - u2.y * invT);
-            const double of = kf * unpack_c(L.C, a, 0) * unpack_c(L.C, a, 1) * unpack_c(L.C, a, 2);
-            const double orv = kr * unpack_c(L.C, b, 0) * unpack_c(L.C, b, 1) * unpack_c(L.C, b, 2);
-            const double q = of - orv;
-            L.Q[p] = q;
-            L.Q[p + RU * G] = -q;
+            const double of = kf * unpack_c(C, a, 0) * unpack_c(C, a, 1) * unpack_c(C, a, 2);
+            const double orv = kr * unpack_c(C, b, 0) * unpack_c(C, b, 1) * unpack_c(C, b, 2);
+            Q[p] = of - orv;
         }
     }
     wave_sync();
@@ -280,44 +330,48 @@ __device__ __forceinline__ void rhs_eval(const double (&z)[NSL], double P10, dou
     // Net production (E:spec-rate), species equations (E:mass) and the
     // enthalpy sum of the energy equation (E:energy).
     {
-        double acc = 0.0;
-        int pid = L.pbase[g];
-        for (int e2 = 0; e2 < L2; ++e2) {
-            const uint32_t w = L.gather[e2 * G + g];
-            const uint32_t t0 = w & 0xffffu, t1 = w >> 16;
-            acc += L.Q[t0 & TERM_INDEX];
-            if (t0 & TERM_FLUSH) { L.piece[pid++] = acc; acc = 0.0; }
-            acc += L.Q[t1 & TERM_INDEX];
-            if (t1 & TERM_FLUSH) { L.piece[pid++] = acc; acc = 0.0; }
+        const unsigned char *Qb = reinterpret_cast<const unsigned char *>(Q);
+        const uint32_t *tw = L.gather + go;
+        const int half = SEGL >> 1;
+        for (int sg = 0; sg < NSEG; ++sg) {
+            double acc = 0.0;
+#pragma unroll 4
+            for (int e2 = 0; e2 < half; ++e2) {
+                const uint32_t w = tw[(sg * half + e2) * G];
+                acc += *reinterpret_cast<const double *>(Qb + (w & 0xffffu));
+                acc += *reinterpret_cast<const double *>(Qb + (w >> 16));
+            }
+            piece[sg * G + go] = acc;
         }
     }
     wave_sync();
     double hs = 0.0;
 #pragma unroll
     for (int s = 0; s < NSL; ++s) {
-        const int k = s * G + g;
-        const int q0 = L.ps[k], q1 = L.ps[k + 1];
-        double w = 0.0;
-        for (int q = q0; q < q1; ++q) w += L.piece[q];
-        fz[s] = L.spec[F_W * NK + k] * w / rho;
+        const int k = s * G + go;
+        const int q0 = L.ps[2 * k], q1 = L.ps[2 * k + 1], q2 = L.ps[2 * k + 2];
+        double wp = 0.0, wn = 0.0;
+        for (int q = q0; q < q1; ++q) wp += piece[q];
+        for (int q = q1; q < q2; ++q) wn += piece[q];
+        const double w = wp - wn;
+        fz[s] = L.spec[F_W * NK + k] * w * inv_rho;
         hs += hRT[s] * w;
     }
     hs = gsum<G>(hs);
     // dT/dt = -sum_i H_i omega_i / (rho cp); R cancels between H and cp.
-    const double fT = -T * hs / (rho * sYcp);
+    const double fT = -T * hs * inv_rho / sYcp;
     if (g == 0) fz[0] = fT;
 }
 
 // ---------------------------------------------------------------- staging
 
 __device__ __forceinline__ void stage_tables(const Params &p, int G, double *spec_l,
-                                             uint32_t *gather_l, int32_t *ps_l, int32_t *pbase_l,
+                                             uint32_t *gather_l, int32_t *ps_l,
                                              double *units_l, int n_units_l) {
     const int tid = threadIdx.x, nt = blockDim.x;
     for (int i = tid; i < NFIELD * p.NK; i += nt) spec_l[i] = p.tab.spec[i];
-    for (int i = tid; i < p.L2 * G; i += nt) gather_l[i] = p.tab.gather[i];
-    for (int i = tid; i <= p.NK; i += nt) ps_l[i] = p.tab.ps[i];
-    for (int i = tid; i < G; i += nt) pbase_l[i] = p.tab.pbase[i];
+    for (int i = tid; i < p.NSEG * (p.SEGL / 2) * G; i += nt) gather_l[i] = p.tab.gather[i];
+    for (int i = tid; i <= 2 * p.NK; i += nt) ps_l[i] = p.tab.ps[i];
     for (int i = tid; i < n_units_l * UNIT_DOUBLES; i += nt) units_l[i] = p.tab.units[i];
 }
 
@@ -339,45 +393,44 @@ __device__ __forceinline__ void load_unit_regs(const Params &p, UnitRegs<RUC> &u
 // Bytes of per-group control state kept in LDS by the integrator kernels.
 constexpr int STATE_BYTES = 256;
 
-// Doubles of per-group LDS: concentrations, signed net rates (+ zero slot,
-// padded to even), gather pieces (padded to even).
-__host__ __device__ inline size_t group_doubles(int NK, int RU, int G, int NP) {
-    return (size_t)NK + (size_t)2 * RU * G + 2 + (size_t)((NP + 1) & ~1);
+// Doubles of per-group LDS: concentrations, net rates (+ zero slot, padded to
+// even), gather pieces.
+__host__ __device__ inline size_t group_doubles(int NK, int RU, int G, int NSEG) {
+    return (size_t)NK + (size_t)RU * G + 2 + (size_t)NSEG * G;
 }
 
 // Bytes of dynamic LDS for a workgroup of `groups` groups.
-__host__ __device__ inline size_t lds_bytes(int NK, int RU, int G, int L2, int NP, int groups,
+__host__ __device__ inline size_t lds_bytes(int NK, int RU, int G, int NSEG, int SEGL, int groups,
                                             bool units_in_lds) {
     size_t b = (size_t)NFIELD * NK * 8;
     if (units_in_lds) b += (size_t)RU * G * UNIT_DOUBLES * 8;
-    b += (size_t)groups * group_doubles(NK, RU, G, NP) * 8;
+    b += (size_t)groups * group_doubles(NK, RU, G, NSEG) * 8;
     b += (size_t)groups * STATE_BYTES;
-    b += (size_t)L2 * G * 4 + ((size_t)NK + 1) * 4 + (size_t)G * 4;
+    b += (size_t)NSEG * (SEGL / 2) * G * 4 + ((size_t)2 * NK + 1) * 4;
     return b;
 }
 
 struct LdsPtrs {
     double *spec, *units;
     uint32_t *gather;
-    int32_t *ps, *pbase;
+    int32_t *ps;
     double *groups;
     unsigned char *states;
 };
 
-__device__ __forceinline__ LdsPtrs carve(unsigned char *base, int NK, int RU, int G, int L2,
-                                         int NP, int groups, bool units_in_lds) {
+__device__ __forceinline__ LdsPtrs carve(unsigned char *base, int NK, int RU, int G, int NSEG,
+                                         int SEGL, int groups, bool units_in_lds) {
     LdsPtrs l;
     size_t off = 0;
     l.spec = reinterpret_cast<double *>(base + off); off += (size_t)NFIELD * NK * 8;
     l.units = reinterpret_cast<double *>(base + off);
     if (units_in_lds) off += (size_t)RU * G * UNIT_DOUBLES * 8;
     l.groups = reinterpret_cast<double *>(base + off);
-    off += (size_t)groups * group_doubles(NK, RU, G, NP) * 8;
+    off += (size_t)groups * group_doubles(NK, RU, G, NSEG) * 8;
     l.states = base + off;
     off += (size_t)groups * STATE_BYTES;
-    l.gather = reinterpret_cast<uint32_t *>(base + off); off += (size_t)L2 * G * 4;
-    l.ps = reinterpret_cast<int32_t *>(base + off); off += ((size_t)NK + 1) * 4;
-    l.pbase = reinterpret_cast<int32_t *>(base + off);
+    l.gather = reinterpret_cast<uint32_t *>(base + off); off += (size_t)NSEG * (SEGL / 2) * G * 4;
+    l.ps = reinterpret_cast<int32_t *>(base + off);
     return l;
 }
 
@@ -386,29 +439,39 @@ __device__ __forceinline__ LdsPtrs carve(unsigned char *base, int NK, int RU, in
 __device__ __forceinline__ GroupLds group_view(const LdsPtrs &lp, const Params &p, int G,
                                                int gib) {
     GroupLds L;
-    L.spec = lp.spec; L.gather = lp.gather; L.ps = lp.ps; L.pbase = lp.pbase;
+    L.spec = lp.spec; L.gather = lp.gather; L.ps = lp.ps;
     L.units = lp.units;
-    L.C = lp.groups + (size_t)gib * group_doubles(p.NK, p.RU, G, p.NP);
+    L.C = lp.groups + (size_t)gib * group_doubles(p.NK, p.RU, G, p.NSEG);
     L.Q = L.C + p.NK;
-    L.piece = L.Q + 2 * p.RU * G + 2;
+    L.piece = L.Q + p.RU * G + 2;
     return L;
 }
 
 __device__ __forceinline__ void group_init(const GroupLds &L, const Params &p, int G, int g) {
     for (int k = g; k < p.NK; k += G) L.C[k] = (k == p.nS) ? 1.0 : 0.0;
-    if (g == 0) { L.Q[2 * p.RU * G] = 0.0; L.Q[2 * p.RU * G + 1] = 0.0; }
+    if (g == 0) { L.Q[p.RU * G] = 0.0; L.Q[p.RU * G + 1] = 0.0; }
 }
 
 // ------------------------------------------------------- source-term kernel
 
+// Occupancy targets: register-resident reaction parameters, or two state
+// slots per lane, need the register file of two waves per SIMD; the other
+// variants fit three (168 VGPRs) without spilling.
+template <int RUC, int NSL>
+struct Occ {
+    static constexpr bool two = RUC > 0 || NSL > 1;
+    static constexpr int threads = two ? 512 : 768;
+    static constexpr int waves = two ? 2 : 3;
+};
+
 template <int G, int NSL, int RUC>
-__global__ __launch_bounds__(512) void rhs_kernel(Params p) {
+__global__ __launch_bounds__((Occ<RUC, NSL>::threads), (Occ<RUC, NSL>::waves)) void rhs_kernel(Params p) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int groups = blockDim.x / G;
     const int gib = threadIdx.x / G;
     const int g = threadIdx.x % G;
-    LdsPtrs lp = carve(lds_raw, p.NK, p.RU, G, p.L2, p.NP, groups, RUC == 0);
-    stage_tables(p, G, lp.spec, lp.gather, lp.ps, lp.pbase, lp.units, RUC == 0 ? p.RU * G : 0);
+    LdsPtrs lp = carve(lds_raw, p.NK, p.RU, G, p.NSEG, p.SEGL, groups, RUC == 0);
+    stage_tables(p, G, lp.spec, lp.gather, lp.ps, lp.units, RUC == 0 ? p.RU * G : 0);
     GroupLds L = group_view(lp, p, G, gib);
     group_init(L, p, G, g);
     __syncthreads();
@@ -430,7 +493,7 @@ __global__ __launch_bounds__(512) void rhs_kernel(Params p) {
     }
     if (!active) z[0] = (g == 0) ? 1000.0 : z[0];
     const double P10 = active ? p.P[cell] * 10.0 : 1e6;
-    rhs_eval<G, NSL, RUC>(z, P10, fz, L, ur, g, p.NK, p.N, p.RU, p.L2);
+    rhs_eval<G, NSL, RUC>(z, P10, 1.0 / P10, fz, L, ur, g, p.N, p.RU, p.NSEG, p.SEGL);
     if (active) {
 #pragma unroll
         for (int s = 0; s < NSL; ++s) {

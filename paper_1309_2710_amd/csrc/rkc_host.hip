@@ -21,11 +21,10 @@ constexpr double LNA_ZERO = -1e300;        // ln A of a reaction whose rate is i
 // Device tables that depend on the lane-group shape: the species table is
 // laid out with stride NK, the gather is balanced over G lanes.
 struct NkTables {
-    int G = 0, NK = 0, RU = 0, L2 = 0, NP = 0;
+    int G = 0, NK = 0, RU = 0, NSEG = 0, SEGL = 0;
     double *spec = nullptr;
     uint32_t *gather = nullptr;
     int32_t *ps = nullptr;
-    int32_t *pbase = nullptr;
 };
 
 }  // namespace
@@ -78,58 +77,62 @@ double ln_a(double A) { return A > 0.0 ? std::log(A) : LNA_ZERO; }
         if ((expr) != hipSuccess) return RKC_EDEVICE;         \
     } while (0)
 
-// Balanced segmented gather for the net production sum (E:spec-rate): the
-// species-major list of signed-rate indices is cut into G equal runs.
+// Balanced gather for the net production sum (E:spec-rate).  Each species'
+// terms (byte offsets of the units' net rates q, repeated |nu'' - nu'| times),
+// split into positive and negative coefficients, are cut into chunks of at
+// most SEGL terms; chunk c (species-major, positive before negative) runs in
+// lane c % G, segment c / G.  SEGL and NSEG minimise NSEG * (SEGL + 2).
 struct GatherPlan {
-    int L2 = 0, NP = 0;
-    std::vector<uint32_t> words;   // [L2][G]
-    std::vector<int32_t> ps;       // [NK + 1]
-    std::vector<int32_t> pbase;    // [G]
+    int NSEG = 1, SEGL = 2;
+    std::vector<uint32_t> words;   // [NSEG * SEGL / 2][G]
+    std::vector<int32_t> ps;       // [2 NK + 1]
 };
 
 int plan_gather(const rkc_mech *m, int G, int NK, int RU, GatherPlan *gp) {
     const int RUG = RU * G;
-    const uint32_t zero_slot = (uint32_t)(2 * RUG);
-    if (2 * RUG + 1 > (int)rkcdev::TERM_INDEX) return RKC_ENOTSUP;
-    std::vector<uint32_t> idx;   // signed-rate index per term
-    std::vector<int> spk;        // state index of each term
-    for (int i = 0; i < m->nS; ++i)
+    if ((size_t)(RUG + 1) * 8 > rkcdev::TERM_MAX_BYTES) return RKC_ENOTSUP;
+    const uint32_t zero_term = (uint32_t)(RUG * 8);
+    // lists[2 i] positive terms of species i, lists[2 i + 1] negative terms
+    std::vector<std::vector<uint32_t>> lists(2 * (size_t)m->nS);
+    int max_row = 0;
+    for (int i = 0; i < m->nS; ++i) {
         for (const auto &pr : m->rows[i]) {
-            const uint32_t id = pr.second > 0 ? (uint32_t)pr.first : (uint32_t)(pr.first + RUG);
-            for (int r = 0; r < std::abs(pr.second); ++r) {
-                idx.push_back(id);
-                spk.push_back(i + 1);
-            }
+            const uint32_t off = (uint32_t)(pr.first * 8);
+            std::vector<uint32_t> &dst = lists[2 * i + (pr.second < 0 ? 1 : 0)];
+            for (int r = 0; r < std::abs(pr.second); ++r) dst.push_back(off);
         }
-    const int M = (int)idx.size();
-    const int L = std::max(1, (M + G - 1) / G);
-    gp->L2 = (L + 1) / 2;
-    gp->words.assign((size_t)gp->L2 * G, 0u);
-    gp->pbase.assign(G, 0);
-    std::vector<int> piece_sp;   // state index of each piece, in piece order
-    for (int g = 0; g < G; ++g) {
-        gp->pbase[g] = (int)piece_sp.size();
-        const int e0 = std::min(M, g * L), e1 = std::min(M, (g + 1) * L);
-        for (int e = 0; e < 2 * gp->L2; ++e) {
-            uint32_t term = zero_slot;
-            const int t = e0 + e;
-            if (t < e1) {
-                term = idx[t];
-                if (t + 1 == e1 || spk[t + 1] != spk[t]) {
-                    term |= rkcdev::TERM_FLUSH;
-                    piece_sp.push_back(spk[t]);
+        max_row = std::max(max_row, (int)std::max(lists[2 * i].size(), lists[2 * i + 1].size()));
+    }
+    long best = -1;
+    for (int L = 2; L <= std::max(2, max_row + (max_row & 1)); L += 2) {
+        long chunks = 0;
+        for (const auto &t : lists) chunks += ((long)t.size() + L - 1) / L;
+        const long nseg = std::max(1L, (chunks + G - 1) / G);
+        const long cost = nseg * (L + 2);
+        if (best < 0 || cost < best) { best = cost; gp->SEGL = L; gp->NSEG = (int)nseg; }
+    }
+    const int L = gp->SEGL;
+    const int half = L / 2;
+    gp->words.assign((size_t)gp->NSEG * half * G, zero_term | (zero_term << 16));
+    gp->ps.assign(2 * (size_t)NK + 1, 0);
+    int c = 0;
+    for (int k = 0; k < NK; ++k) {
+        for (int sign = 0; sign < 2; ++sign) {
+            gp->ps[2 * k + sign] = c;
+            if (k < 1 || k > m->nS) continue;
+            const std::vector<uint32_t> &t = lists[2 * (k - 1) + sign];
+            for (size_t b = 0; b < t.size(); b += L, ++c) {
+                const int g = c % G, sg = c / G;
+                for (int e = 0; e < L; ++e) {
+                    const uint32_t term = (b + e < t.size()) ? t[b + e] : zero_term;
+                    uint32_t &w = gp->words[(size_t)(sg * half + e / 2) * G + g];
+                    w = (e % 2) ? ((w & 0xffffu) | (term << 16)) : ((w & 0xffff0000u) | term);
                 }
             }
-            gp->words[(size_t)(e / 2) * G + g] |= term << (16 * (e % 2));
         }
     }
-    gp->NP = (int)piece_sp.size();
-    gp->ps.assign(NK + 1, 0);
-    int q = 0;
-    for (int k = 0; k <= NK; ++k) {
-        while (q < gp->NP && piece_sp[q] < k) ++q;
-        gp->ps[k] = q;
-    }
+    gp->ps[2 * NK] = c;
+    if (c > gp->NSEG * G) return RKC_ENOTSUP;   // cannot happen by construction
     return RKC_OK;
 }
 
@@ -164,19 +167,17 @@ int ensure_tables(rkc_mech *m, int G, int NK, int RU, NkTables **out) {
     t.G = G;
     t.NK = NK;
     t.RU = RU;
-    t.L2 = gp.L2;
-    t.NP = gp.NP;
+    t.NSEG = gp.NSEG;
+    t.SEGL = gp.SEGL;
     if (hipMalloc(&t.spec, spec.size() * 8) != hipSuccess) return RKC_ENOMEM;
     if (hipMalloc(&t.gather, gp.words.size() * 4) != hipSuccess ||
-        hipMalloc(&t.ps, gp.ps.size() * 4) != hipSuccess ||
-        hipMalloc(&t.pbase, gp.pbase.size() * 4) != hipSuccess) {
-        (void)hipFree(t.spec); (void)hipFree(t.gather); (void)hipFree(t.ps);
+        hipMalloc(&t.ps, gp.ps.size() * 4) != hipSuccess) {
+        (void)hipFree(t.spec); (void)hipFree(t.gather);
         return RKC_ENOMEM;
     }
     HIP_OK(hipMemcpy(t.spec, spec.data(), spec.size() * 8, hipMemcpyHostToDevice));
     HIP_OK(hipMemcpy(t.gather, gp.words.data(), gp.words.size() * 4, hipMemcpyHostToDevice));
     HIP_OK(hipMemcpy(t.ps, gp.ps.data(), gp.ps.size() * 4, hipMemcpyHostToDevice));
-    HIP_OK(hipMemcpy(t.pbase, gp.pbase.data(), gp.pbase.size() * 4, hipMemcpyHostToDevice));
     m->nk.push_back(t);
     *out = &m->nk.back();
     return RKC_OK;
@@ -187,7 +188,7 @@ struct Choice {
     int RU;
 };
 
-int choose_variant(const rkc_mech *m, int lanes, Choice *out) {
+int choose_variant(const rkc_mech *m, int lanes, int placement, Choice *out) {
     int G = lanes;
     if (G == 0) G = (m->N >= 40) ? 64 : (m->N > 16 ? 32 : 16);
     int n = 0;
@@ -206,8 +207,9 @@ int choose_variant(const rkc_mech *m, int lanes, Choice *out) {
         if (tab[i].NSL >= nsl_need) best_nsl = std::min(best_nsl, tab[i].NSL);
     if (best_nsl == (1 << 30)) return RKC_ENOTSUP;
     const rkchost::VariantDesc *pick = nullptr;
-    for (int i = 0; i < n; ++i)
-        if (tab[i].NSL == best_nsl && tab[i].RUC == ru) pick = &tab[i];
+    if (placement == RKC_PARAMS_REGISTERS)
+        for (int i = 0; i < n; ++i)
+            if (tab[i].NSL == best_nsl && tab[i].RUC == ru) pick = &tab[i];
     if (!pick)
         for (int i = 0; i < n; ++i)
             if (tab[i].NSL == best_nsl && tab[i].RUC == 0) pick = &tab[i];
@@ -242,10 +244,11 @@ int plan_launch(const rkc_mech *m, const Choice &ch, const void *kernel, size_t 
                 const rkc_opts &o, bool allow_persistent, NkTables *nk, Launch *L) {
     const int G = ch.v.G;
     const int NK = nk->NK;
-    int gpb = o.block_groups > 0 ? o.block_groups : std::max(1, 256 / G);
-    if (gpb * G > 512) gpb = 512 / G;
+    const int max_threads = ch.v.max_threads;
+    int gpb = o.block_groups > 0 ? o.block_groups : std::max(1, max_threads / G);
+    if (gpb * G > max_threads) gpb = max_threads / G;
     auto need = [&](int groups) {
-        return rkcdev::lds_bytes(NK, ch.RU, G, nk->L2, nk->NP, groups, ch.v.RUC == 0);
+        return rkcdev::lds_bytes(NK, ch.RU, G, nk->NSEG, nk->SEGL, groups, ch.v.RUC == 0);
     };
     while (gpb > 1 && need(gpb) > m->max_lds) gpb = (gpb + 1) / 2;
     if (need(gpb) > m->max_lds) return RKC_ENOTSUP;
@@ -284,13 +287,12 @@ void fill_params(const rkc_mech *m, const Choice &ch, const NkTables *nk, rkcdev
     p->NK = nk->NK;
     p->nU = m->nU;
     p->RU = ch.RU;
-    p->L2 = nk->L2;
-    p->NP = nk->NP;
+    p->NSEG = nk->NSEG;
+    p->SEGL = nk->SEGL;
     p->tab.units = m->units_d;
     p->tab.spec = nk->spec;
     p->tab.gather = nk->gather;
     p->tab.ps = nk->ps;
-    p->tab.pbase = nk->pbase;
     p->agg = m->agg_d;
     p->queue = m->queue_d;
 }
@@ -331,7 +333,6 @@ int rkc_mech_destroy(rkc_mech *m) {
         (void)hipFree(t.spec);
         (void)hipFree(t.gather);
         (void)hipFree(t.ps);
-        (void)hipFree(t.pbase);
     }
     if (m->agg_d) (void)hipFree(m->agg_d);
     if (m->queue_d) (void)hipFree(m->queue_d);
@@ -472,7 +473,7 @@ int rkc_rhs(const rkc_mech *mc, size_t n, const double *T, const double *P, cons
     HIP_OK(hipGetDevice(&cur));
     if (cur != m->device) HIP_OK(hipSetDevice(m->device));
     Choice ch;
-    int rc = choose_variant(m, o.lanes_per_cell, &ch);
+    int rc = choose_variant(m, o.lanes_per_cell, o.param_placement, &ch);
     if (rc) return rc;
     NkTables *nk = nullptr;
     rc = ensure_tables(m, ch.v.G, ch.v.NSL * ch.v.G, ch.RU, &nk);
@@ -526,7 +527,8 @@ int rkc_integrate(const rkc_mech *mc, size_t n, double *T, const double *P, doub
         return RKC_EINVAL;
     if (o.method != RKC_METHOD_RKC && o.method != RKC_METHOD_RKCK) return RKC_EINVAL;
     if (o.s_max < 2 || o.max_steps < 1) return RKC_EINVAL;
-    if (o.schedule < 0 || o.schedule > 2 || o.block_groups < 0 || o.grid_blocks < 0)
+    if (o.schedule < 0 || o.schedule > 2 || o.block_groups < 0 || o.grid_blocks < 0 ||
+        o.param_placement < 0 || o.param_placement > 2)
         return RKC_EINVAL;
     if (stats) std::memset(stats, 0, sizeof(*stats));
     if (n == 0) return RKC_OK;
@@ -536,7 +538,7 @@ int rkc_integrate(const rkc_mech *mc, size_t n, double *T, const double *P, doub
     HIP_OK(hipGetDevice(&cur));
     if (cur != m->device) HIP_OK(hipSetDevice(m->device));
     Choice ch;
-    int rc = choose_variant(m, o.lanes_per_cell, &ch);
+    int rc = choose_variant(m, o.lanes_per_cell, o.param_placement, &ch);
     if (rc) return rc;
     NkTables *nk = nullptr;
     rc = ensure_tables(m, ch.v.G, ch.v.NSL * ch.v.G, ch.RU, &nk);

@@ -150,9 +150,8 @@ __device__ __forceinline__ double rms_norm(const double (&d)[NSL], const double 
     const int groups = blockDim.x / G;                                                       \
     const int gib = threadIdx.x / G;                                                         \
     const int g = threadIdx.x % G;                                                           \
-    LdsPtrs lp = carve(lds_raw, p.NK, p.RU, G, p.L2, p.NP, groups, RUC == 0);                \
-    stage_tables(p, G, lp.spec, lp.gather, lp.ps, lp.pbase, lp.units,                        \
-                 RUC == 0 ? p.RU * G : 0);                                                   \
+    LdsPtrs lp = carve(lds_raw, p.NK, p.RU, G, p.NSEG, p.SEGL, groups, RUC == 0);            \
+    stage_tables(p, G, lp.spec, lp.gather, lp.ps, lp.units, RUC == 0 ? p.RU * G : 0);        \
     GroupLds L = group_view(lp, p, G, gib);                                                  \
     group_init(L, p, G, g);                                                                  \
     __syncthreads();                                                                         \
@@ -168,8 +167,8 @@ __device__ __forceinline__ double rms_norm(const double (&d)[NSL], const double 
 // between source-term evaluations, so it does not occupy registers while the
 // evaluation runs.  Every lane of the group writes identical values.
 struct RkcState {
-    double t, h, sigma, sigma_prev, delta, ht, h_prev, err_prev, P10;
-    double w0, w1, Tm1, Tm2, Tpm1, Tpm2, Tppm1, Tppm2, bm1, bm2;
+    double t, h, sigma, sigma_prev, delta, ht, h_prev, lerr_prev, P10, invP10;
+    double w0, w1, Tm1, Tm2, Tpm1, Tpm2, Tppm1, Tppm2, bm1, ibm1, ibm2;
     int cell, phase, k_pow, s, j, last, need_sigma, since_sigma, predictive, after;
     Counts c;
 };
@@ -181,7 +180,7 @@ enum { ACT_NONE = 0, ACT_BEGIN_STEP, ACT_AFTER_SIGMA, ACT_POWER_INIT, ACT_POWER_
 // ------------------------------------------------------------------- RKC
 
 template <int G, int NSL, int RUC>
-__global__ __launch_bounds__(512) void rkc_kernel(Params p) {
+__global__ __launch_bounds__((Occ<RUC, NSL>::threads), (Occ<RUC, NSL>::waves)) void rkc_kernel(Params p) {
     RKC_KERNEL_PROLOGUE
     const double sqrt_u = sqrt(u_round);
     RkcState &S = *reinterpret_cast<RkcState *>(lp.states + (size_t)gib * STATE_BYTES);
@@ -193,6 +192,7 @@ __global__ __launch_bounds__(512) void rkc_kernel(Params p) {
         z[i] = (i == 0 && g == 0) ? 1000.0 : 0.0;
     }
     S.P10 = 1e6;
+    S.invP10 = 1e-6;
 
     // Take the next valid cell starting at `first` (cells with bad input are
     // marked and skipped); S.cell = -1 when the queue is exhausted.
@@ -203,9 +203,10 @@ __global__ __launch_bounds__(512) void rkc_kernel(Params p) {
             if (load_state<G, NSL>(p, cell, g, y, P10)) {
                 S.cell = cell;
                 S.P10 = P10;
+                S.invP10 = 1.0 / P10;
                 S.c = Counts{0, 0, 0, 0, 0, 0, 0};
                 S.t = 0.0; S.need_sigma = 0; S.since_sigma = 0; S.predictive = 0;
-                S.h_prev = 0.0; S.err_prev = 0.0;
+                S.h_prev = 0.0; S.lerr_prev = 0.0;
 #pragma unroll
                 for (int i = 0; i < NSL; ++i) z[i] = y[i];
                 S.phase = PH_F0;
@@ -222,22 +223,25 @@ __global__ __launch_bounds__(512) void rkc_kernel(Params p) {
     acquire(blockIdx.x * groups + gib);
 
     for (;;) {
-        rhs_eval<G, NSL, RUC>(z, S.P10, fz, L, ur, g, p.NK, N, p.RU, p.L2);
+        rhs_eval<G, NSL, RUC>(z, S.P10, S.invP10, fz, L, ur, g, N, p.RU, p.NSEG, p.SEGL);
         if (S.cell >= 0) {
             Counts c = S.c;
             c.n_rhs += 1;
             int act = ACT_NONE, fin = ST_OK;
             const int phase = S.phase;
             if (phase == PH_STAGE) {
-                // (E:rkcj) with the coefficient recurrences advanced one stage
+                // (E:rkcj) with the coefficient recurrences advanced one stage;
+                // 1/b_{j-1} and 1/b_{j-2} are carried, so a stage needs two
+                // divisions (b_j and 1/b_j)
                 const double w0 = S.w0, Tm1 = S.Tm1, Tpm1 = S.Tpm1, Tppm1 = S.Tppm1, bm1 = S.bm1;
+                const double ibm1 = S.ibm1;
                 const double Tj = 2.0 * w0 * Tm1 - S.Tm2;
                 const double Tpj = 2.0 * w0 * Tpm1 - S.Tpm2 + 2.0 * Tm1;
                 const double Tppj = 2.0 * w0 * Tppm1 - S.Tppm2 + 4.0 * Tpm1;
                 const double bj = Tppj / (Tpj * Tpj);
-                const double mu = 2.0 * bj * w0 / bm1;
-                const double nu = -bj / S.bm2;
-                const double mut = 2.0 * bj * S.w1 / bm1;
+                const double mu = 2.0 * bj * w0 * ibm1;
+                const double nu = -bj * S.ibm2;
+                const double mut = 2.0 * bj * S.w1 * ibm1;
                 const double gam = -(1.0 - bm1 * Tm1) * mut;
                 const double h = S.h;
                 const double c0 = 1.0 - mu - nu, ch1 = mut * h, ch2 = gam * h;
@@ -249,7 +253,7 @@ __global__ __launch_bounds__(512) void rkc_kernel(Params p) {
                     z[i] = wj;
                 }
                 S.Tm2 = Tm1; S.Tm1 = Tj; S.Tpm2 = Tpm1; S.Tpm1 = Tpj; S.Tppm2 = Tppm1; S.Tppm1 = Tppj;
-                S.bm2 = bm1; S.bm1 = bj;
+                S.bm1 = bj; S.ibm2 = ibm1; S.ibm1 = 1.0 / bj;
                 const int j = S.j;
                 if (j == S.s) S.phase = PH_ERR;
                 else S.j = j + 1;
@@ -273,21 +277,23 @@ __global__ __launch_bounds__(512) void rkc_kernel(Params p) {
                         const int ss = S.since_sigma + 1;
                         S.since_sigma = ss;
                         S.need_sigma = (ss >= 25);
+                        // err^a as exp(a log err): one logarithm per step
+                        const double lerr = log_pos(err);
                         double fac;
                         if (err == 0.0) fac = 10.0;
-                        else if (!S.predictive) fac = 0.8 * pow(err, -1.0 / 3.0);
-                        else fac = 0.8 * (h / S.h_prev) * pow(S.err_prev, 1.0 / 3.0) * pow(err, -2.0 / 3.0);
+                        else if (!S.predictive) fac = 0.8 * exp(-lerr / 3.0);
+                        else fac = 0.8 * (h / S.h_prev) * exp((S.lerr_prev - 2.0 * lerr) / 3.0);
                         if (fac > 10.0) fac = 10.0;
                         if (fac < 0.1) fac = 0.1;
                         S.h_prev = h;
-                        S.err_prev = err;
+                        S.lerr_prev = lerr;
                         S.predictive = 1;
                         S.h = h * fac;
                         act = ACT_BEGIN_STEP;
                     }
                 } else {
                     c.n_reject += 1;
-                    double fac = isfinite(err) ? 0.8 * pow(err, -1.0 / 3.0) : 0.1;
+                    double fac = isfinite(err) ? 0.8 * exp(-log_pos(err) / 3.0) : 0.1;
                     if (fac < 0.1) fac = 0.1;
                     S.h = h * fac;
                     S.need_sigma = 1;
@@ -443,7 +449,7 @@ __global__ __launch_bounds__(512) void rkc_kernel(Params p) {
                 const double b2 = Q2 / (P2 * P2);
                 S.w0 = w0; S.w1 = w1;
                 S.Tm1 = w0; S.Tm2 = 1.0; S.Tpm1 = 1.0; S.Tpm2 = 0.0; S.Tppm1 = 0.0; S.Tppm2 = 0.0;
-                S.bm1 = b1; S.bm2 = b2;   // b_0 = b_2
+                S.bm1 = b1; S.ibm1 = w0; S.ibm2 = 1.0 / b2;   // b_1 = 1/w0, b_0 = b_2
                 S.h = h; S.last = last; S.s = s; S.j = 2;
                 const double mu_t1 = b1 * w1;
 #pragma unroll
@@ -496,14 +502,14 @@ __global__ __launch_bounds__(512) void rkc_kernel(Params p) {
 #define CK_D6 (512.0 / 1771.0 - 1.0 / 4.0)
 
 struct RkckState {
-    double t, h, P10;
+    double t, h, P10, invP10;
     int cell, phase, last;
     Counts c;
 };
 static_assert(sizeof(RkckState) <= STATE_BYTES, "RKCK state exceeds its LDS slot");
 
 template <int G, int NSL, int RUC>
-__global__ __launch_bounds__(512) void rkck_kernel(Params p) {
+__global__ __launch_bounds__((Occ<RUC, NSL>::threads), (Occ<RUC, NSL>::waves)) void rkck_kernel(Params p) {
     RKC_KERNEL_PROLOGUE
     RkckState &S = *reinterpret_cast<RkckState *>(lp.states + (size_t)gib * STATE_BYTES);
 
@@ -514,6 +520,7 @@ __global__ __launch_bounds__(512) void rkck_kernel(Params p) {
         z[i] = (i == 0 && g == 0) ? 1000.0 : 0.0;
     }
     S.P10 = 1e6;
+    S.invP10 = 1e-6;
 
     auto acquire = [&](int first) {
         int cell = first;
@@ -522,6 +529,7 @@ __global__ __launch_bounds__(512) void rkck_kernel(Params p) {
             if (load_state<G, NSL>(p, cell, g, y, P10)) {
                 S.cell = cell;
                 S.P10 = P10;
+                S.invP10 = 1.0 / P10;
                 S.c = Counts{0, 0, 0, 0, 0, 0, 0};
                 S.t = 0.0;
                 // first trial step is the whole interval; the last step lands on dt
@@ -543,7 +551,7 @@ __global__ __launch_bounds__(512) void rkck_kernel(Params p) {
     acquire(blockIdx.x * groups + gib);
 
     for (;;) {
-        rhs_eval<G, NSL, RUC>(z, S.P10, fz, L, ur, g, p.NK, N, p.RU, p.L2);
+        rhs_eval<G, NSL, RUC>(z, S.P10, S.invP10, fz, L, ur, g, N, p.RU, p.NSEG, p.SEGL);
         if (S.cell >= 0) {
             Counts c = S.c;
             c.n_rhs += 1;
@@ -617,13 +625,13 @@ __global__ __launch_bounds__(512) void rkck_kernel(Params p) {
                         fin = ST_OK;
                     } else {
                         S.t = S.t + h;
-                        double fac = (errmax == 0.0) ? 5.0 : 0.9 * pow(errmax, -0.2);
+                        double fac = (errmax == 0.0) ? 5.0 : 0.9 * exp(-0.2 * log_pos(errmax));
                         if (fac > 5.0) fac = 5.0;
                         hn = h * fac;
                     }
                 } else {
                     c.n_reject += 1;
-                    double fac = isfinite(errmax) ? 0.9 * pow(errmax, -0.25) : 0.1;
+                    double fac = isfinite(errmax) ? 0.9 * exp(-0.25 * log_pos(errmax)) : 0.1;
                     if (fac < 0.1) fac = 0.1;
                     hn = h * fac;
                 }

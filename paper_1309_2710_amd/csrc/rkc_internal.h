@@ -12,6 +12,7 @@ namespace rkchost {
 // any number of units).
 struct VariantDesc {
     int G, NSL, RUC;
+    int max_threads;
     const void *k_rkc;
     const void *k_rkck;
     const void *k_rhs;
@@ -26,7 +27,7 @@ const VariantDesc *variants_g8(int *n);
 
 #define RKC_VARIANT(G_, NSL_, RUC_)                                                            \
     rkchost::VariantDesc {                                                                     \
-        G_, NSL_, RUC_,                                                                        \
+        G_, NSL_, RUC_, (rkcdev::Occ<RUC_, NSL_>::threads),                                          \
             reinterpret_cast<const void *>(&rkcdev::rkc_kernel<G_, NSL_, RUC_>),               \
             reinterpret_cast<const void *>(&rkcdev::rkck_kernel<G_, NSL_, RUC_>),              \
             reinterpret_cast<const void *>(&rkcdev::rhs_kernel<G_, NSL_, RUC_>)                \

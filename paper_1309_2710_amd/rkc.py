@@ -23,6 +23,7 @@ OK, EINVAL, ENOMEM, EDEVICE, ECELLS, ENOTSUP = 0, -1, -2, -3, -4, -5
 CELL_OK, CELL_UNDERFLOW, CELL_MAXSTEPS, CELL_NONFINITE, CELL_BADINPUT = 0, 1, 2, 3, 4
 RKC, RKCK = 0, 1
 SCHED_AUTO, SCHED_PLAIN, SCHED_PERSISTENT = 0, 1, 2
+PARAMS_AUTO, PARAMS_REGISTERS, PARAMS_LDS = 0, 1, 2
 NCOUNTERS = 8
 COUNTER_FIELDS = ["n_rhs", "n_steps", "n_reject", "n_sigma", "s_max_used", "s_hash", "status",
                   "n_power_iter"]
@@ -43,7 +44,7 @@ class Opts(ct.Structure):
                 ("lanes_per_cell", ct.c_int32), ("schedule", ct.c_int32),
                 ("block_groups", ct.c_int32), ("grid_blocks", ct.c_int32),
                 ("device_ptrs", ct.c_int32), ("stream", ct.c_void_p),
-                ("cell_counters", ct.c_void_p)]
+                ("cell_counters", ct.c_void_p), ("param_placement", ct.c_int32)]
 
 
 class Stats(ct.Structure):
@@ -165,7 +166,7 @@ def _is_torch(x):
 
 def make_opts(method=RKC, s_max=1000, max_steps=1000000, lanes_per_cell=0,
               schedule=SCHED_AUTO, block_groups=0, grid_blocks=0, device_ptrs=False,
-              stream=None, cell_counters=None):
+              stream=None, cell_counters=None, param_placement=PARAMS_AUTO):
     o = Opts()
     lib().rkc_opts_default(ct.byref(o))
     o.method = int(method)
@@ -178,6 +179,7 @@ def make_opts(method=RKC, s_max=1000, max_steps=1000000, lanes_per_cell=0,
     o.device_ptrs = 1 if device_ptrs else 0
     o.stream = stream
     o.cell_counters = cell_counters
+    o.param_placement = int(param_placement)
     return o
 
 
@@ -191,7 +193,7 @@ def _stream_handle(stream, tensors):
 def integrate(mech, T, P, Y, dt, rtol=1e-6, atol=1e-10, method=RKC, lanes_per_cell=0,
               schedule=SCHED_AUTO, block_groups=0, grid_blocks=0, s_max=1000,
               max_steps=1000000, counters=False, status=True, stats=False, stream=None,
-              check=True):
+              check=True, param_placement=PARAMS_AUTO):
     """Integrate cells over [0, dt] in place.
 
     numpy inputs: T [n] and Y [n][nS] are overwritten in place (must be
@@ -223,7 +225,7 @@ def integrate(mech, T, P, Y, dt, rtol=1e-6, atol=1e-10, method=RKC, lanes_per_ce
         cp = _np_ptr(cn_t) if counters else None
         strm = ct.c_void_p(stream) if isinstance(stream, int) else None
     o = make_opts(method, s_max, max_steps, lanes_per_cell, schedule, block_groups, grid_blocks,
-                  dev, strm, cp)
+                  dev, strm, cp, param_placement)
     s = Stats()
     rc = L.rkc_integrate(mech.handle, n, ptrs[0], ptrs[1], ptrs[2], float(dt), float(rtol),
                          float(atol), ct.byref(o), sp, ct.byref(s) if stats else None)
