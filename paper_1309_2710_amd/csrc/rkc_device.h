@@ -51,12 +51,12 @@ enum {
 
 // Reaction unit record: 8 doubles.
 //   [0..2] ln A, beta, theta = Ea/R of the forward reaction
-//   [3..5] the same for the reverse reaction (ln A = -1e300 for an unpaired
-//          reaction, so its reverse rate is exactly zero)
-//   [6]    bit pattern: low 32 bits forward reactant slots, high 32 bits
-//          reverse reactant slots; three 10-bit species indices each, the
-//          value n_species meaning an empty slot (LDS C[n_species] == 1.0)
-//   [7]    0
+//   [3..5] the same for the reverse reaction (ln A = -1e4 for an unpaired
+//          reaction, so its reverse rate underflows to exactly zero)
+//   [6]    bit pattern: forward reactant slots, three 16-bit byte offsets
+//          into the concentration array (bits 0..47); an empty slot points
+//          at C[n_species], which holds 1.0
+//   [7]    bit pattern: the reverse reaction's reactant slots, same layout
 constexpr int UNIT_DOUBLES = 8;
 
 struct Tables {
@@ -206,6 +206,32 @@ __device__ __forceinline__ double unpack_c(const double *C, uint32_t id, int s) 
     return C[(id >> (10 * s)) & 1023u];
 }
 
+// exp(x) for |x| < 1e9: Cody & Waite reduction x = n ln2 + r, |r| <= ln2/2,
+// with ln2 split into its double rounding and the remainder, then the Taylor
+// polynomial of exp(r) through r^13 (truncation < 2^-57 relative) by Horner,
+// scaled by 2^n.  Underflows to exactly 0 below about -745; NaN propagates.
+// Within about one ulp; written so every Horner step is one FMA.
+__device__ __forceinline__ double exp_cw(double x) {
+    const double n = __builtin_rint(x * 0x1.71547652b82fep+0);
+    const double r = __builtin_fma(-n, 0x1.abc9e3b39803fp-56,
+                                   __builtin_fma(-n, 0x1.62e42fefa39efp-1, x));
+    double q = 1.0 / 6227020800.0;
+    q = __builtin_fma(q, r, 1.0 / 479001600.0);
+    q = __builtin_fma(q, r, 1.0 / 39916800.0);
+    q = __builtin_fma(q, r, 1.0 / 3628800.0);
+    q = __builtin_fma(q, r, 1.0 / 362880.0);
+    q = __builtin_fma(q, r, 1.0 / 40320.0);
+    q = __builtin_fma(q, r, 1.0 / 5040.0);
+    q = __builtin_fma(q, r, 1.0 / 720.0);
+    q = __builtin_fma(q, r, 1.0 / 120.0);
+    q = __builtin_fma(q, r, 1.0 / 24.0);
+    q = __builtin_fma(q, r, 1.0 / 6.0);
+    q = __builtin_fma(q, r, 0.5);
+    q = __builtin_fma(q, r, 1.0);
+    q = __builtin_fma(q, r, 1.0);
+    return __builtin_ldexp(q, (int)n);
+}
+
 // Natural logarithm of a positive finite double (NaN otherwise).  Argument
 // reduction x = m 2^e with m in [sqrt(1/2), sqrt(2)), then
 // log x = e ln2 + 2 atanh(s), s = (m - 1)/(m + 1), |s| <= 0.1716, with the odd
@@ -302,8 +328,8 @@ __device__ __forceinline__ void rhs_eval(const double (&z)[NSL], double P10, dou
         double q[RUC];
 #pragma unroll
         for (int r = 0; r < RUC; ++r) {
-            const double kf = exp(ur.lnAf[r] + ur.bf[r] * lnT - ur.tf[r] * invT);
-            const double kr = exp(ur.lnAr[r] + ur.br[r] * lnT - ur.tr[r] * invT);
+            const double kf = exp_cw(ur.lnAf[r] + ur.bf[r] * lnT - ur.tf[r] * invT);
+            const double kr = exp_cw(ur.lnAr[r] + ur.br[r] * lnT - ur.tr[r] * invT);
             const uint32_t a = ur.idf[r] + oz, b = ur.idr[r] + oz;
             const double of = kf * unpack_c(C, a, 0) * unpack_c(C, a, 1) * unpack_c(C, a, 2);
             const double orv = kr * unpack_c(C, b, 0) * unpack_c(C, b, 1) * unpack_c(C, b, 2);
@@ -316,12 +342,15 @@ __device__ __forceinline__ void rhs_eval(const double (&z)[NSL], double P10, dou
             const int p = r * G + g;
             const double2 *u = reinterpret_cast<const double2 *>(L.units + (size_t)p * UNIT_DOUBLES);
             const double2 u0 = u[0], u1 = u[1], u2 = u[2], u3 = u[3];
-            const uint64_t bits = __double_as_longlong(u3.x);
-            const uint32_t a = (uint32_t)bits, b = (uint32_t)(bits >> 32);
-            const double kf = exp(u0.x + u0.y * lnT - u1.x * invT);
-            const double kr = exp(u1.y + u2.x * lnT - u2.y * invT);
-            const double of = kf * unpack_c(C, a, 0) * unpack_c(C, a, 1) * unpack_c(C, a, 2);
-            const double orv = kr * unpack_c(C, b, 0) * unpack_c(C, b, 1) * unpack_c(C, b, 2);
+            const uint64_t a = __double_as_longlong(u3.x), b = __double_as_longlong(u3.y);
+            const double kf = exp_cw(u0.x + u0.y * lnT - u1.x * invT);
+            const double kr = exp_cw(u1.y + u2.x * lnT - u2.y * invT);
+            const unsigned char *Cb = reinterpret_cast<const unsigned char *>(C);
+            auto cat = [&](uint64_t o, int sl) {
+                return *reinterpret_cast<const double *>(Cb + ((o >> (16 * sl)) & 0xffffu));
+            };
+            const double of = kf * cat(a, 0) * cat(a, 1) * cat(a, 2);
+            const double orv = kr * cat(b, 0) * cat(b, 1) * cat(b, 2);
             Q[p] = of - orv;
         }
     }
@@ -383,9 +412,15 @@ __device__ __forceinline__ void load_unit_regs(const Params &p, UnitRegs<RUC> &u
             const double *u = p.tab.units + (size_t)(r * G + g) * UNIT_DOUBLES;
             ur.lnAf[r] = u[0]; ur.bf[r] = u[1]; ur.tf[r] = u[2];
             ur.lnAr[r] = u[3]; ur.br[r] = u[4]; ur.tr[r] = u[5];
-            const uint64_t bits = __double_as_longlong(u[6]);
-            ur.idf[r] = (uint32_t)bits;
-            ur.idr[r] = (uint32_t)(bits >> 32);
+            // 16-bit byte offsets -> three 10-bit indices
+            const uint64_t bf = __double_as_longlong(u[6]), br = __double_as_longlong(u[7]);
+            uint32_t f = 0, v = 0;
+            for (int sl = 0; sl < 3; ++sl) {
+                f |= (uint32_t)(((bf >> (16 * sl)) & 0xffffu) >> 3) << (10 * sl);
+                v |= (uint32_t)(((br >> (16 * sl)) & 0xffffu) >> 3) << (10 * sl);
+            }
+            ur.idf[r] = f;
+            ur.idr[r] = v;
         }
     }
 }

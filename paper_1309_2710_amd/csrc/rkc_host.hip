@@ -16,7 +16,7 @@ using rkcdev::UNIT_DOUBLES;
 namespace {
 
 constexpr double R_J = 8.31446261815324;   // J/(mol K)
-constexpr double LNA_ZERO = -1e300;        // ln A of a reaction whose rate is identically 0
+constexpr double LNA_ZERO = -1e4;          // ln A of a reaction whose rate is identically 0
 
 // Device tables that depend on the lane-group shape: the species table is
 // laid out with stride NK, the gather is balanced over G lanes.
@@ -61,11 +61,13 @@ bool same_multiset(const int32_t *a, const int32_t *b) {
     return x[0] == y[0] && x[1] == y[1] && x[2] == y[2];
 }
 
-uint32_t pack_slots(const int32_t *slots, int nS) {
-    uint32_t v = 0;
+// Three reactant slots as 16-bit byte offsets into the concentration array;
+// an empty slot points at index n_species (which holds 1.0).
+uint64_t pack_slots(const int32_t *slots, int nS) {
+    uint64_t v = 0;
     for (int s = 0; s < 3; ++s) {
-        const uint32_t id = slots[s] >= 0 ? (uint32_t)slots[s] : (uint32_t)nS;
-        v |= id << (10 * s);
+        const uint64_t id = slots[s] >= 0 ? (uint64_t)slots[s] : (uint64_t)nS;
+        v |= (id * 8u) << (16 * s);
     }
     return v;
 }
@@ -400,8 +402,9 @@ int rkc_mech_create(const rkc_mech_desc *d, rkc_mech **out) {
             const int32_t none[3] = {-1, -1, -1};
             idr = pack_slots(none, nS);
         }
-        const uint64_t bits = (uint64_t)pack_slots(rf, nS) | (idr << 32);
-        std::memcpy(&rec[6], &bits, 8);
+        const uint64_t idf = pack_slots(rf, nS);
+        std::memcpy(&rec[6], &idf, 8);
+        std::memcpy(&rec[7], &idr, 8);
         units.insert(units.end(), rec, rec + UNIT_DOUBLES);
         for (int i = 0; i < nS; ++i) {
             const int dnu = count_in(pf, i) - count_in(rf, i);
@@ -416,8 +419,9 @@ int rkc_mech_create(const rkc_mech_desc *d, rkc_mech **out) {
     double pad[UNIT_DOUBLES] = {0};
     {
         const int32_t none[3] = {-1, -1, -1};
-        const uint64_t bits = (uint64_t)pack_slots(none, nS) | ((uint64_t)pack_slots(none, nS) << 32);
+        const uint64_t bits = pack_slots(none, nS);
         std::memcpy(&pad[6], &bits, 8);
+        std::memcpy(&pad[7], &bits, 8);
     }
     for (int q = p; q < m->nU_pad; ++q) units.insert(units.end(), pad, pad + UNIT_DOUBLES);
     m->units_h = units;

@@ -281,8 +281,8 @@ __global__ __launch_bounds__((Occ<RUC, NSL>::threads), (Occ<RUC, NSL>::waves)) v
                         const double lerr = log_pos(err);
                         double fac;
                         if (err == 0.0) fac = 10.0;
-                        else if (!S.predictive) fac = 0.8 * exp(-lerr / 3.0);
-                        else fac = 0.8 * (h / S.h_prev) * exp((S.lerr_prev - 2.0 * lerr) / 3.0);
+                        else if (!S.predictive) fac = 0.8 * exp_cw(-lerr / 3.0);
+                        else fac = 0.8 * (h / S.h_prev) * exp_cw((S.lerr_prev - 2.0 * lerr) / 3.0);
                         if (fac > 10.0) fac = 10.0;
                         if (fac < 0.1) fac = 0.1;
                         S.h_prev = h;
@@ -293,7 +293,7 @@ __global__ __launch_bounds__((Occ<RUC, NSL>::threads), (Occ<RUC, NSL>::waves)) v
                     }
                 } else {
                     c.n_reject += 1;
-                    double fac = isfinite(err) ? 0.8 * exp(-log_pos(err) / 3.0) : 0.1;
+                    double fac = isfinite(err) ? 0.8 * exp_cw(-log_pos(err) / 3.0) : 0.1;
                     if (fac < 0.1) fac = 0.1;
                     S.h = h * fac;
                     S.need_sigma = 1;
@@ -625,13 +625,13 @@ __global__ __launch_bounds__((Occ<RUC, NSL>::threads), (Occ<RUC, NSL>::waves)) v
                         fin = ST_OK;
                     } else {
                         S.t = S.t + h;
-                        double fac = (errmax == 0.0) ? 5.0 : 0.9 * exp(-0.2 * log_pos(errmax));
+                        double fac = (errmax == 0.0) ? 5.0 : 0.9 * exp_cw(-0.2 * log_pos(errmax));
                         if (fac > 5.0) fac = 5.0;
                         hn = h * fac;
                     }
                 } else {
                     c.n_reject += 1;
-                    double fac = isfinite(errmax) ? 0.9 * exp(-0.25 * log_pos(errmax)) : 0.1;
+                    double fac = isfinite(errmax) ? 0.9 * exp_cw(-0.25 * log_pos(errmax)) : 0.1;
                     if (fac < 0.1) fac = 0.1;
                     hn = h * fac;
                 }
