@@ -16,6 +16,7 @@ serial FP64 oracle timed on a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -59,10 +60,46 @@ def rhs_flops(mech):
     return f
 
 
+def kernel_source_hash():
+    """sha256 over the HIP sources of the library (host and device code)."""
+    d = os.path.join(ROOT, "paper_1309_2710_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".h", ".hip")):
+            h.update(f.encode())
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload):
+    """HBM bytes per launch of the integrator from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE passes, each scaled by the same counter
+    on a copy kernel of known size), or None when no summary matches the
+    current sources and workload."""
+    path = os.path.join(ROOT, "profiles", "rkc_kernel_%s_traffic.txt" % workload)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(kv["bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def stage_flops(mech):
     """Flops of one RKC stage update (E:rkcj) per RHS evaluation: 1 mul + 4 FMA
     per state component."""
     return 9 * (mech["n_species"] + 1)
+
+
+def workload_tag(mech, n):
+    return "%dsp%drx_%dcells" % (mech["n_species"], mech["n_reactions"], n)
 
 
 def main():
@@ -75,7 +112,23 @@ def main():
     ap.add_argument("--schedule", type=int, default=0)
     ap.add_argument("--params", type=int, default=0, help="0 auto, 1 registers, 2 LDS")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="choose schedule and workgroup size with rkc_autotune on a strided "
+                         "sample of 16384 cells before the census (results do not change)")
+    ap.add_argument("--graph", action="store_true",
+                    help="time replays of a recorded global step (rkc_graph_create) instead of "
+                         "rkc_integrate calls")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--serve", action="store_true",
+                    help="replay the served mixed-request trace (13/53 species, Poisson "
+                         "arrivals) through the integration server and, as the baseline, "
+                         "through sequential rkc_integrate calls; report latency")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-streams", type=int, default=4)
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="run one device copy kernel of this many MiB (read + write) after the "
+                         "timed region: the known-size reference for HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only; the cells of a global step "
@@ -86,6 +139,10 @@ def main():
     import torch
 
     from paper_1309_2710_amd import rkc, synth
+
+    if args.serve:
+        serve(args)
+        return
 
     cfg = args.config
     c = synth.CONFIGS[cfg]
@@ -101,6 +158,13 @@ def main():
     Y = Y0.clone()
     kw = dict(lanes_per_cell=args.lanes, schedule=args.schedule, status=False,
               param_placement=args.params)
+    tuned = None
+    if args.autotune:
+        idx = torch.arange(0, n, max(1, n // 16384), device=dev)[:16384]
+        tuned, tuned_ms = rkc.autotune(gm, T0[idx].contiguous(), P[idx].contiguous(),
+                                       Y0[idx].contiguous(), c["dt"], c["rtol"], c["atol"],
+                                       lanes_per_cell=args.lanes, param_placement=args.params)
+        kw.update(schedule=tuned["schedule"], block_groups=tuned["block_groups"])
 
     # Warm-up and work census: the K timed steps are replayed once untimed with
     # statistics (results are bitwise deterministic, so the timed run performs
@@ -119,6 +183,12 @@ def main():
     Y.copy_(Y0)
     torch.cuda.synchronize()
 
+    graph = None
+    if args.graph:
+        graph = rkc.Graph(gm, T, P, Y, c["dt"], c["rtol"], c["atol"], lanes_per_cell=args.lanes,
+                          schedule=kw["schedule"], block_groups=kw.get("block_groups", 0),
+                          param_placement=args.params)
+
     # Timed region: K consecutive global steps, device-resident state.
     stream = torch.cuda.current_stream(dev)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
@@ -126,12 +196,43 @@ def main():
     t0 = time.perf_counter()
     ev[0].record(stream)
     for k in range(args.steps):
-        rkc.integrate(gm, T, P, Y, c["dt"], c["rtol"], c["atol"], **kw)
+        if graph is not None:
+            graph.launch(stream)
+        else:
+            rkc.integrate(gm, T, P, Y, c["dt"], c["rtol"], c["atol"], **kw)
         ev[k + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     step_ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)]
     ms_per_step = wall * 1e3 / args.steps
+
+    # One more global step from the final state with host arrays: the rate
+    # including the PCIe copies (reported beside `value`, never as it).
+    Th, Yh = T.cpu().numpy().copy(), Y.cpu().numpy().copy()
+    Ph = P.cpu().numpy()
+    Td, Yd = T.clone(), Y.clone()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    rkc.integrate(gm, Td, P, Yd, c["dt"], c["rtol"], c["atol"], **kw)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    dev_ms = e0.elapsed_time(e1)
+    a = time.perf_counter()
+    rkc.integrate(gm, Th, Ph, Yh, c["dt"], c["rtol"], c["atol"], **kw)
+    host_ms = (time.perf_counter() - a) * 1e3
+    pcie = {"step_ms_host_arrays": host_ms, "step_ms_device_arrays": dev_ms,
+            "cells_per_s_host_arrays": n / host_ms * 1e3,
+            "note": "one global step after the timed ones; host arrays add the H2D and D2H "
+                    "copies of the state"}
+    del Td, Yd
+
+    if args.copy_mib > 0:
+        src = torch.ones(args.copy_mib * (1 << 20) // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
 
     f_rhs = rhs_flops(mech)
     f_stage = stage_flops(mech)
@@ -158,18 +259,169 @@ def main():
                    "dt": c["dt"], "rtol": c["rtol"], "atol": c["atol"],
                    "lanes_per_cell": census[0]["lanes_per_cell"],
                    "schedule": ["auto", "plain", "persistent"][census[0]["schedule"]],
+                   "launch": "hip graph replay" if graph is not None else "rkc_integrate",
+                   "autotuned": tuned,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None},
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+                     "traffic": measured_traffic(workload_tag(mech, n))},
+        "pcie_inclusive": pcie,
         "work": {"rhs_evals_per_step": tot_rhs / args.steps, "flops_per_rhs": f_rhs,
                  "flops_per_stage_update": f_stage,
                  "mean_rhs_per_cell": tot_rhs / args.steps / n,
                  "kernel_ms_per_step": step_ms,
                  "steps_per_cell": sum(s["n_steps"] for s in census) / args.steps / n,
+                 "rhs_utilisation": tot_rhs / max(1, sum(s["n_rhs_slots"] for s in census)),
                  "s_max_used": max(s["s_max_used"] for s in census)},
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(mech, c, st, args.steps, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def serve_inputs(trace, synth):
+    """Per-request input copies: each request takes a contiguous run of cells
+    from a seeded pool of states of its mechanism (65536 cells, the largest
+    request), starting at an offset drawn from its state seed."""
+    pools = {}
+    reqs = []
+    for r in trace:
+        key = r["mech"]
+        if key not in pools:
+            kind, i = key
+            base = "c2" if kind == 13 else "c3"
+            c = synth.CONFIGS[base]
+            pools[key] = synth.make_states(synth.c5_mechanism(kind, i), 1 << 16,
+                                           synth.C5_SEED * 10 + kind * 4 + i,
+                                           T_dist=c["T"], P_dist=c["P"], Y_dist=c["Y"])
+        pool = pools[key]
+        n = r["n_cells"]
+        o = r["state_seed"] % ((1 << 16) - n + 1)
+        reqs.append({"T": pool["T"][o:o + n].copy(), "P": pool["P"][o:o + n].copy(),
+                     "Y": pool["Y"][o:o + n].copy()})
+    return reqs
+
+
+def serve(args):
+    """Served workload: the mixed-request trace replayed at its arrival times
+    through the server (submission thread sleeping until each arrival), and
+    the same trace served by sequential rkc_integrate calls as the baseline."""
+    import threading
+
+    from paper_1309_2710_amd import rkc, synth
+
+    trace = synth.c5_trace(n_requests=args.serve_requests, rate=args.serve_rate)
+    keys = sorted({r["mech"] for r in trace})
+    mechs = {k: synth.c5_mechanism(*k) for k in keys}
+    span = trace[-1]["t_arrival"]
+    cells = sum(r["n_cells"] for r in trace)
+
+    # baseline: one synchronous rkc_integrate per request in arrival order
+    gms = {k: rkc.Mechanism(m) for k, m in mechs.items()}
+    inp = serve_inputs(trace, synth)
+    for r, x in zip(trace, inp):   # first-use table builds outside the timed replay
+        if r["mech"] in keys:
+            keys = [k for k in keys if k != r["mech"]]
+            rkc.integrate(gms[r["mech"]], x["T"][:1].copy(), x["P"][:1].copy(),
+                          x["Y"][:1].copy(), r["dt"])
+    busy = 0.0
+    lat_b = []
+    base_status = np.zeros(5, np.int64)
+    t0 = time.perf_counter()
+    for r, x in zip(trace, inp):
+        now = time.perf_counter() - t0
+        if now < r["t_arrival"]:
+            time.sleep(r["t_arrival"] - now)
+        c = synth.CONFIGS["c2" if r["mech"][0] == 13 else "c3"]
+        a = time.perf_counter()
+        o = rkc.integrate(gms[r["mech"]], x["T"], x["P"], x["Y"], r["dt"], c["rtol"],
+                          c["atol"])
+        b = time.perf_counter()
+        base_status += np.bincount(o["status"], minlength=5)[:5]
+        if (len(lat_b) + 1) % 100 == 0:
+            print("baseline: %d/%d requests, %.1f s" % (len(lat_b) + 1, len(trace),
+                                                        time.perf_counter() - t0),
+                  file=sys.stderr, flush=True)
+        busy += b - a
+        lat_b.append((b - t0 - r["t_arrival"]) * 1e3)
+    base_wall = time.perf_counter() - t0
+    del gms
+
+    # served: the same trace through the server
+    inp = serve_inputs(trace, synth)
+    srv = rkc.Server(budget_bytes=4 << 30, n_streams=args.serve_streams)
+    ids = {k: srv.register(m) for k, m in mechs.items()}
+    rids = [None] * len(trace)
+    done = threading.Event()
+
+    def waiter():
+        for i in range(len(trace)):
+            while rids[i] is None:
+                time.sleep(1e-4)
+            srv.wait(rids[i])
+            if (i + 1) % 100 == 0:
+                print("served: %d/%d completed, %.1f s" % (i + 1, len(trace),
+                                                           time.perf_counter() - t0),
+                      file=sys.stderr, flush=True)
+        done.set()
+
+    th = threading.Thread(target=waiter)
+    srv.reset_stats()
+    t0 = time.perf_counter()
+    th.start()
+    for i, (r, x) in enumerate(zip(trace, inp)):
+        now = time.perf_counter() - t0
+        if now < r["t_arrival"]:
+            time.sleep(r["t_arrival"] - now)
+        c = synth.CONFIGS["c2" if r["mech"][0] == 13 else "c3"]
+        x["S"] = np.empty(r["n_cells"], np.int32)
+        rids[i] = srv.submit(ids[r["mech"]], x["T"], x["P"], x["Y"], r["dt"], c["rtol"],
+                             c["atol"], status=x["S"])
+        if (i + 1) % 200 == 0:
+            print("served: %d/%d submitted, %.1f s" % (i + 1, len(trace), time.perf_counter() - t0),
+                  file=sys.stderr, flush=True)
+    th.join()
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    served_status = np.zeros(5, np.int64)
+    failures = []
+    for i, (r, x) in enumerate(zip(trace, inp)):
+        h = np.bincount(x["S"], minlength=5)[:5]
+        served_status += h
+        if h[1:].sum() and len(failures) < 10:
+            failures.append({"request": i, "mech": list(r["mech"]), "dt": r["dt"],
+                             "n_cells": r["n_cells"], "status_counts": h.tolist(),
+                             "first_failed_cell": int(np.nonzero(x["S"])[0][0])})
+
+    def pct(v, q):
+        v = sorted(v)
+        return v[min(len(v), max(1, int(np.ceil(q * len(v))))) - 1]
+
+    out = {
+        "metric": "p99 request latency, served mixed 13/53-species trace (FP64)",
+        "value": st["p99_ms"],
+        "unit": "ms",
+        "n_gpus": 1,
+        "higher_is_better": False,
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "c5: %d requests, Poisson %.0f req/s over %.2f s, 2^U(10,16) "
+                               "cells, 13/53 species, dt 1e-6/1e-5" % (len(trace), args.serve_rate,
+                                                                        span),
+                   "cells": cells, "n_streams": args.serve_streams},
+        "served": {"p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"],
+                   "max_ms": st["max_ms"], "wall_s": wall, "cells_per_s": cells / wall,
+                   "launches": st["launches"], "peak_queue": st["peak_queue"],
+                   "peak_bytes": st["peak_bytes"], "failed_requests": st["failed_requests"],
+                   "cell_status_counts": served_status.tolist(), "failures": failures},
+        "sequential_baseline": {"p50_ms": pct(lat_b, 0.5), "p99_ms": pct(lat_b, 0.99),
+                                "wall_s": base_wall, "busy_s": busy,
+                                "cell_status_counts": base_status.tolist(),
+                                "cells_per_s": cells / busy},
+        "offered_utilisation": busy / span,
+    }
     print(json.dumps(out), flush=True)
 
 

@@ -77,6 +77,7 @@ enum { RKC_CNT_RHS = 0, RKC_CNT_STEPS = 1, RKC_CNT_REJECT = 2, RKC_CNT_SIGMA = 3
        RKC_CNT_SMAX = 4, RKC_CNT_SHASH = 5, RKC_CNT_STATUS = 6, RKC_CNT_POWER_ITER = 7 };
 
 typedef struct rkc_mech rkc_mech;   /* opaque, owned by the library */
+typedef struct rkc_graph rkc_graph; /* opaque, owned by the library */
 
 /* Mechanism description: irreversible reactions with Arrhenius rates
  * (E:rxn-const), mass-action rates of progress (E:rxn-rate) and two-range
@@ -132,6 +133,11 @@ typedef struct {
     int32_t grid_blocks;     /* workgroups launched */
     int32_t block_threads;   /* threads per workgroup */
     int32_t lds_bytes;       /* dynamic LDS per workgroup */
+    int64_t n_rhs_slots;     /* source-term evaluations the lane groups issued: every
+                                iteration of the integrator loop issues one per group,
+                                whether or not the group still holds a cell, so
+                                n_rhs / n_rhs_slots is the fraction of issued work that
+                                advanced a cell (1 = no idle groups) */
 } rkc_stats;
 
 /* Fill *opts with the defaults.  Returns RKC_EINVAL for NULL. */
@@ -177,6 +183,56 @@ int rkc_rhs(const rkc_mech *mech, size_t n, const double *T, const double *P,
 int rkc_integrate(const rkc_mech *mech, size_t n_cells, double *T, const double *P,
                   double *Y, double dt, double rtol, double atol, const rkc_opts *opts,
                   int32_t *cell_status, rkc_stats *stats);
+
+/* Choose the launch grain for a workload by timing it: runs rkc_integrate
+ * over the given cells (left unchanged: the runs use internal copies) with
+ * each candidate setting of the options that never change results --
+ * schedule (persistent, plain) and lane groups per workgroup (the largest,
+ * half and a quarter) -- and writes *opts with the fastest into *tuned (every
+ * other field copied from *opts).  *best_ms (may be NULL) receives its time.
+ * A sample of the real cells is the intended input.  Arrays are host or
+ * device pointers per opts->device_ptrs; opts may be NULL (defaults).
+ * Errors: RKC_EINVAL, RKC_ENOTSUP, RKC_ENOMEM, RKC_EDEVICE. */
+int rkc_autotune(const rkc_mech *mech, size_t n_cells, const double *T, const double *P,
+                 const double *Y, double dt, double rtol, double atol, const rkc_opts *opts,
+                 rkc_opts *tuned, float *best_ms);
+
+/* Record the device work of one rkc_integrate call with device arrays as a
+ * HIP graph, for repeated launches with the same arrays and sizes (one
+ * replay = one global step, as in the paper's repeated global steps of
+ * Sec. 3).  opts->device_ptrs must be 1 and every array (T, P, Y,
+ * cell_status, opts->cell_counters) stays bound to the graph, which owns its
+ * own scratch: replays never share state with other calls on the handle.
+ * Mechanism tables and launch attributes are prepared before recording, so
+ * nothing is allocated while recording; the graph holds no memset nodes.
+ * Errors: RKC_EINVAL (host arrays, NULL, n_cells = 0, bad scalars),
+ * RKC_ENOTSUP, RKC_ENOMEM, RKC_EDEVICE. */
+int rkc_graph_create(const rkc_mech *mech, size_t n_cells, double *T, const double *P,
+                     double *Y, double dt, double rtol, double atol, const rkc_opts *opts,
+                     int32_t *cell_status, rkc_graph **out);
+
+/* Enqueue one replay on stream (hipStream_t, NULL = null stream). */
+int rkc_graph_launch(rkc_graph *graph, void *stream);
+
+/* Release a graph; NULL is accepted. */
+int rkc_graph_destroy(rkc_graph *graph);
+
+/* Divergence measure D of Sec. 3.2 (results section, divergence of GPU
+ * threads), for runs of `width` consecutive cells:
+ *   D_r = (sum_{i in run r} d_i) / (c_r * max_{i in run r} d_i),
+ * d_i = work[i * stride] >= 0 the work of cell i (the paper uses its number of
+ * source-term evaluations, e.g. the RKC_CNT_RHS column of cell_counters with
+ * stride RKC_NCOUNTERS, or a per-cell sum over several global steps with
+ * stride 1), c_r = width except for a shorter last run, and D_r = 1 when every
+ * d_i of the run is 0.  width 32 is the paper's warp; 64 a wavefront of
+ * cells.  D = 1 means equal work, D -> 1/c_r one cell doing all of it.
+ *   D [ceil(n_cells / width)] output.
+ * Arrays are host pointers unless opts->device_ptrs (then device pointers,
+ * enqueued on opts->stream); opts may be NULL.  Runs on the current device.
+ * Returns RKC_OK, RKC_EINVAL (stride or width < 1, NULL array), RKC_ENOMEM,
+ * RKC_ENOTSUP (sizes beyond 2^31 cells) or RKC_EDEVICE; n_cells = 0 is a no-op. */
+int rkc_divergence(size_t n_cells, const int32_t *work, int32_t stride, int32_t width,
+                   double *D, const rkc_opts *opts);
 
 /* Static string for a return code. */
 const char *rkc_strerror(int code);

@@ -150,3 +150,16 @@ def rkc_coeffs(s):
     a = [np.zeros(s + 1) for _ in range(4)]
     lib().orc_rkc_coeffs(int(s), *[_p(x) for x in a])
     return tuple(a)
+
+
+def divergence(d, width=32):
+    """Divergence measure D of Sec. 3.2 for consecutive runs of `width` cells:
+    the run's total work over (run length x its largest work); 1 for a run
+    whose work is all zero.  Plain loops over the definition."""
+    d = [int(x) for x in d]
+    out = []
+    for first in range(0, len(d), width):
+        run = d[first:first + width]
+        mx = max(run)
+        out.append(1.0 if mx == 0 else float(sum(run)) / (float(len(run)) * float(mx)))
+    return np.array(out, dtype=np.float64)

@@ -83,11 +83,21 @@ struct Params {
     int s_max, max_steps;
     int32_t *cell_status;            // optional
     int32_t *cell_counters;          // optional [n][8]
-    unsigned long long *agg;         // [8] aggregate counters
+    unsigned long long *agg;         // [16] aggregate counters
+    const double *coef;              // RKC stage coefficients for s <= coef_smax (see
+                                     // coef_offset), or null
+    int coef_smax;
+    double invN;                     // 1 / N
     int *queue;                      // persistent work-queue head
     int persistent;
     int groups_total;                // groups in the launched grid
 };
+
+// RKC stage coefficients (E:rkc1, E:rkcj) depend on the stage count s and
+// the stage j only.  For s <= coef_smax they are read from a table of 4
+// doubles per (s, j), j = 1..s, starting at entry coef_offset(s): entry j = 1
+// holds (mu~_1, 0, 0, 0), entry j >= 2 (mu_j, nu_j, mu~_j, gamma~_j).
+__host__ __device__ inline int coef_offset(int s) { return (s - 1) * s / 2 - 1; }
 
 // ---------------------------------------------------------------- helpers
 
@@ -232,35 +242,34 @@ __device__ __forceinline__ double exp_cw(double x) {
     return __builtin_ldexp(q, (int)n);
 }
 
-// Natural logarithm of a positive finite double (NaN otherwise).  Argument
-// reduction x = m 2^e with m in [sqrt(1/2), sqrt(2)), then
-// log x = e ln2 + 2 atanh(s), s = (m - 1)/(m + 1), |s| <= 0.1716, with the odd
-// Taylor series of atanh through s^23 (truncation below 2^-60 relative); ln 2
-// is split into a head with trailing zero bits and a tail (Cody & Waite) so
-// e * ln2_hi is exact.  Within one ulp of the correctly rounded value.
+// Natural logarithm of a positive finite double (NaN otherwise).  With
+// x = m 2^e, m in [1/2, 1), a single-precision estimate l0 of ln m (hardware
+// base-2 logarithm times ln 2, relative error ~1e-7) is corrected exactly:
+// d = m exp(-l0) - 1 is tiny (|d| < 1e-6), ln m = l0 + ln(1 + d), and the
+// series d - d^2/2 + d^3/3 of ln(1 + d) leaves a truncation below d^4/4.
+// The error is that of exp_cw (about 1e-16 absolute); ln 2 is split into a
+// head with trailing zero bits and a tail so that e ln2_hi is exact.  No
+// division and no polynomial table beyond the exponential's.
 __device__ __forceinline__ double log_pos(double x) {
     int e;
-    double m = frexp(x, &e);
-    const bool lo = m < 0.70710678118654752440;
-    m = lo ? 2.0 * m : m;
-    e = lo ? e - 1 : e;
-    const double s = (m - 1.0) / (m + 1.0);
-    const double s2 = s * s;
-    double q = 1.0 / 23.0;
-    q = q * s2 + 1.0 / 21.0;
-    q = q * s2 + 1.0 / 19.0;
-    q = q * s2 + 1.0 / 17.0;
-    q = q * s2 + 1.0 / 15.0;
-    q = q * s2 + 1.0 / 13.0;
-    q = q * s2 + 1.0 / 11.0;
-    q = q * s2 + 1.0 / 9.0;
-    q = q * s2 + 1.0 / 7.0;
-    q = q * s2 + 1.0 / 5.0;
-    q = q * s2 + 1.0 / 3.0;
+    const double m = frexp(x, &e);
+    const double l0 = (double)__builtin_amdgcn_logf((float)m) * 0x1.62e42fefa39efp-1;
+    const double d = __builtin_fma(m, exp_cw(-l0), -1.0);
+    const double lm = l0 + d * __builtin_fma(d, __builtin_fma(d, 1.0 / 3.0, -0.5), 1.0);
     const double ln2_hi = 0x1.62e42fee00000p-1, ln2_lo = 0x1.a39ef35793c76p-33;
     const double de = (double)e;
-    const double r = (de * ln2_hi + 2.0 * s) + (de * ln2_lo + (2.0 * s * s2) * q);
+    const double r = __builtin_fma(de, ln2_hi, __builtin_fma(de, ln2_lo, lm));
     return (x > 0.0 && x <= 0x1.fffffffffffffp+1023) ? r : __builtin_nan("");
+}
+
+// 1/x for a positive normal x: hardware reciprocal refined by two Newton
+// steps (each doubles the correct bits; the result is within an ulp).
+__device__ __forceinline__ double rcp_nr(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-x, r, 1.0);
+    return __builtin_fma(r, e, r);
 }
 
 // A zero the compiler cannot see through.  Adding it to loop-invariant table
@@ -283,7 +292,7 @@ __device__ __forceinline__ void rhs_eval(const double (&z)[NSL], double P10, dou
     const uint32_t oz = opaque_zero();
     const int go = g + (int)oz;
     const double T = gbcast0<G>(z[0]);
-    const double invT = 1.0 / T;
+    const double invT = rcp_nr(T);
     const double lnT = log_pos(T);
 
     double sYW = 0.0, sYcp = 0.0;
@@ -305,7 +314,7 @@ __device__ __forceinline__ void rhs_eval(const double (&z)[NSL], double P10, dou
     }
     gsum2<G>(sYW, sYcp);
     const double RTW = R_ERG * T * sYW;
-    const double rho = P10 / RTW;          // ideal gas, g/cm^3
+    const double rho = P10 * rcp_nr(RTW);  // ideal gas, g/cm^3
     const double inv_rho = RTW * invP10;
 
     // The C, Q and piece arrays never overlap; telling the compiler so lets it
@@ -388,7 +397,7 @@ __device__ __forceinline__ void rhs_eval(const double (&z)[NSL], double P10, dou
     }
     hs = gsum<G>(hs);
     // dT/dt = -sum_i H_i omega_i / (rho cp); R cancels between H and cp.
-    const double fT = -T * hs * inv_rho / sYcp;
+    const double fT = -T * hs * inv_rho * rcp_nr(sYcp);
     if (g == 0) fz[0] = fT;
 }
 
@@ -426,7 +435,7 @@ __device__ __forceinline__ void load_unit_regs(const Params &p, UnitRegs<RUC> &u
 }
 
 // Bytes of per-group control state kept in LDS by the integrator kernels.
-constexpr int STATE_BYTES = 256;
+constexpr int STATE_BYTES = 320;
 
 // Doubles of per-group LDS: concentrations, net rates (+ zero slot, padded to
 // even), gather pieces.
@@ -489,14 +498,14 @@ __device__ __forceinline__ void group_init(const GroupLds &L, const Params &p, i
 
 // ------------------------------------------------------- source-term kernel
 
-// Occupancy targets: register-resident reaction parameters, or two state
-// slots per lane, need the register file of two waves per SIMD; the other
-// variants fit three (168 VGPRs) without spilling.
+// Occupancy targets (waves per SIMD; a workgroup holds one wave per SIMD per
+// target wave): register-resident reaction parameters, or four state slots
+// per lane, need the register file of two waves; two slots fit three waves
+// (168 VGPRs) and one slot fits four (128 VGPRs), all without spilling.
 template <int RUC, int NSL>
 struct Occ {
-    static constexpr bool two = RUC > 0 || NSL > 1;
-    static constexpr int threads = two ? 512 : 768;
-    static constexpr int waves = two ? 2 : 3;
+    static constexpr int waves = (RUC > 0 || NSL > 2) ? 2 : (NSL == 2 ? 3 : 4);
+    static constexpr int threads = waves * 256;
 };
 
 template <int G, int NSL, int RUC>

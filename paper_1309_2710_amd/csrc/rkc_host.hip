@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -16,6 +17,7 @@ using rkcdev::UNIT_DOUBLES;
 namespace {
 
 constexpr double R_J = 8.31446261815324;   // J/(mol K)
+using rkchost::AGG_N;
 constexpr double LNA_ZERO = -1e4;          // ln A of a reaction whose rate is identically 0
 
 // Device tables that depend on the lane-group shape: the species table is
@@ -29,6 +31,14 @@ struct NkTables {
 
 }  // namespace
 
+struct rkc_graph {
+    int device = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    unsigned long long *agg_d = nullptr;
+    int *queue_d = nullptr;
+};
+
 struct rkc_mech {
     int device = 0;
     int nS = 0, nR = 0, N = 0, nU = 0, nU_pad = 0, nnz = 0, max_row = 0;
@@ -37,7 +47,8 @@ struct rkc_mech {
     std::vector<std::vector<std::pair<int, int>>> rows;  // species -> (unit, dnu)
     double *units_d = nullptr;
     std::vector<NkTables> nk;
-    unsigned long long *agg_d = nullptr;               // [8]
+    unsigned long long *agg_d = nullptr;               // [AGG_N]
+    double *coef_d = nullptr;                          // RKC stage coefficient table
     int *queue_d = nullptr;
     void *stage_d = nullptr;
     size_t stage_bytes = 0;
@@ -74,9 +85,54 @@ uint64_t pack_slots(const int32_t *slots, int nS) {
 
 double ln_a(double A) { return A > 0.0 ? std::log(A) : LNA_ZERO; }
 
-#define HIP_OK(expr)                                          \
-    do {                                                      \
-        if ((expr) != hipSuccess) return RKC_EDEVICE;         \
+// Stage counts whose RKC coefficients are tabulated (larger ones are computed
+// by the kernels' recurrences).
+constexpr int COEF_SMAX = 128;
+
+// The coefficient table described at rkcdev::coef_offset, for s = 2..COEF_SMAX
+// (Sec. 2.4: Chebyshev values at w0 = 1 + kappa/s^2 by their recurrences,
+// b_j = T''_j / T'_j^2 for j >= 2, b_1 = 1/w0, b_0 = b_2, a_j = 1 - b_j T_j).
+std::vector<double> coef_table() {
+    std::vector<double> t(4 * (size_t)rkcdev::coef_offset(COEF_SMAX + 1), 0.0);
+    for (int s = 2; s <= COEF_SMAX; ++s) {
+        const double w0 = 1.0 + rkcdev::KAPPA / ((double)s * (double)s);
+        std::vector<double> T(s + 1), Tp(s + 1), Tpp(s + 1), b(s + 1);
+        T[0] = 1.0; T[1] = w0; Tp[0] = 0.0; Tp[1] = 1.0; Tpp[0] = 0.0; Tpp[1] = 0.0;
+        for (int j = 2; j <= s; ++j) {
+            T[j] = 2.0 * w0 * T[j - 1] - T[j - 2];
+            Tp[j] = 2.0 * w0 * Tp[j - 1] - Tp[j - 2] + 2.0 * T[j - 1];
+            Tpp[j] = 2.0 * w0 * Tpp[j - 1] - Tpp[j - 2] + 4.0 * Tp[j - 1];
+        }
+        const double w1 = Tp[s] / Tpp[s];
+        for (int j = 2; j <= s; ++j) b[j] = Tpp[j] / (Tp[j] * Tp[j]);
+        b[1] = 1.0 / w0;
+        b[0] = b[2];
+        double *e = &t[4 * (size_t)rkcdev::coef_offset(s)];
+        e[0] = b[1] * w1;
+        for (int j = 2; j <= s; ++j) {
+            double *q = e + 4 * (j - 1);
+            q[0] = 2.0 * b[j] * w0 / b[j - 1];
+            q[1] = -b[j] / b[j - 2];
+            q[2] = 2.0 * b[j] * w1 / b[j - 1];
+            q[3] = -(1.0 - b[j - 1] * T[j - 1]) * q[2];
+        }
+    }
+    return t;
+}
+
+// A failed HIP call returns RKC_EDEVICE; with RKC_DEBUG set in the
+// environment it is also reported on stderr.
+bool hip_failed(hipError_t e, const char *what, int line) {
+    if (e == hipSuccess) return false;
+    if (std::getenv("RKC_DEBUG"))
+        std::fprintf(stderr, "rkc: %s failed at rkc_host.hip:%d: %s\n", what, line,
+                     hipGetErrorString(e));
+    return true;
+}
+
+#define HIP_OK(expr)                                                    \
+    do {                                                                \
+        if (hip_failed((expr), #expr, __LINE__)) return RKC_EDEVICE;    \
     } while (0)
 
 // Balanced gather for the net production sum (E:spec-rate).  Each species'
@@ -232,7 +288,7 @@ int ensure_stage(rkc_mech *m, size_t bytes) {
 }
 
 __global__ void reset_scratch_kernel(unsigned long long *agg, int *queue) {
-    if (threadIdx.x < 8) agg[threadIdx.x] = 0ull;
+    if (threadIdx.x < AGG_N) agg[threadIdx.x] = 0ull;
     if (threadIdx.x == 0) *queue = 0;
 }
 
@@ -252,7 +308,7 @@ int plan_launch(const rkc_mech *m, const Choice &ch, const void *kernel, size_t 
     auto need = [&](int groups) {
         return rkcdev::lds_bytes(NK, ch.RU, G, nk->NSEG, nk->SEGL, groups, ch.v.RUC == 0);
     };
-    while (gpb > 1 && need(gpb) > m->max_lds) gpb = (gpb + 1) / 2;
+    while (gpb > 1 && need(gpb) > m->max_lds) --gpb;
     if (need(gpb) > m->max_lds) return RKC_ENOTSUP;
     L->groups_per_block = gpb;
     L->threads = gpb * G;
@@ -297,9 +353,130 @@ void fill_params(const rkc_mech *m, const Choice &ch, const NkTables *nk, rkcdev
     p->tab.ps = nk->ps;
     p->agg = m->agg_d;
     p->queue = m->queue_d;
+    p->coef = m->coef_d;
+    p->coef_smax = m->coef_d ? COEF_SMAX : 0;
+    p->invN = 1.0 / (double)m->N;
+}
+
+// Divergence measure of a run of consecutive cells (Sec. 3.2): the work of the
+// run over `width` times its largest member's work.
+__global__ void divergence_kernel(const int32_t *w, int stride, long long n, int width,
+                                  double *D) {
+    const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long first = r * (long long)width;
+    if (first >= n) return;
+    const long long last = first + width < n ? first + width : n;
+    long long sum = 0;
+    int mx = 0;
+    for (long long i = first; i < last; ++i) {
+        const int d = w[i * stride];
+        sum += d;
+        mx = d > mx ? d : mx;
+    }
+    D[r] = mx > 0 ? (double)sum / ((double)(last - first) * (double)mx) : 1.0;
 }
 
 }  // namespace
+
+namespace rkchost {
+
+int check_integrate_args(double dt, double rtol, double atol, const rkc_opts &o) {
+    if (!(dt > 0.0) || !std::isfinite(dt) || !(rtol > 0.0) || !std::isfinite(rtol) ||
+        !(atol >= 0.0) || !std::isfinite(atol))
+        return RKC_EINVAL;
+    if (o.method != RKC_METHOD_RKC && o.method != RKC_METHOD_RKCK) return RKC_EINVAL;
+    if (o.s_max < 2 || o.max_steps < 1) return RKC_EINVAL;
+    if (o.schedule < 0 || o.schedule > 2 || o.block_groups < 0 || o.grid_blocks < 0 ||
+        o.param_placement < 0 || o.param_placement > 2)
+        return RKC_EINVAL;
+    return RKC_OK;
+}
+
+int enqueue_integrate(rkc_mech *m, size_t n, double *Td, const double *Pd, double *Yd, double dt,
+                      double rtol, double atol, const rkc_opts &o, int32_t *sd, int32_t *cd,
+                      unsigned long long *agg_d, int *queue_d, hipStream_t st, LaunchInfo *li) {
+    Choice ch;
+    int rc = choose_variant(m, o.lanes_per_cell, o.param_placement, &ch);
+    if (rc) return rc;
+    NkTables *nk = nullptr;
+    rc = ensure_tables(m, ch.v.G, ch.v.NSL * ch.v.G, ch.RU, &nk);
+    if (rc) return rc;
+    const void *kernel = o.method == RKC_METHOD_RKC ? ch.v.k_rkc : ch.v.k_rkck;
+    Launch L;
+    rc = plan_launch(m, ch, kernel, n, o, true, nk, &L);
+    if (rc) return rc;
+    // launch errors are taken from the launch call itself: the thread's last
+    // error can hold an unrelated earlier status (e.g. a not-ready query made
+    // by other code in the process)
+    {
+        void *rargs[] = {&agg_d, &queue_d};
+        HIP_OK(hipLaunchKernel(reinterpret_cast<const void *>(&reset_scratch_kernel), dim3(1),
+                               dim3(64), rargs, 0, st));
+    }
+    rkcdev::Params p;
+    fill_params(m, ch, nk, &p);
+    p.agg = agg_d;
+    p.queue = queue_d;
+    p.n_cells = (int)n;
+    p.T = Td;
+    p.P = Pd;
+    p.Y = Yd;
+    p.dt = dt;
+    p.rtol = rtol;
+    p.atol = atol;
+    p.s_max = o.s_max;
+    p.max_steps = o.max_steps;
+    p.cell_status = sd;
+    p.cell_counters = cd;
+    p.persistent = L.persistent ? 1 : 0;
+    p.groups_total = L.blocks * L.groups_per_block;
+    void *args[] = {&p};
+    HIP_OK(hipLaunchKernel(kernel, dim3(L.blocks), dim3(L.threads), args, L.lds, st));
+    li->G = ch.v.G;
+    li->persistent = L.persistent;
+    li->blocks = L.blocks;
+    li->threads = L.threads;
+    li->lds = L.lds;
+    return RKC_OK;
+}
+
+int prepare(rkc_mech *m, const rkc_opts &o, size_t n_cells) {
+    Choice ch;
+    int rc = choose_variant(m, o.lanes_per_cell, o.param_placement, &ch);
+    if (rc) return rc;
+    NkTables *nk = nullptr;
+    rc = ensure_tables(m, ch.v.G, ch.v.NSL * ch.v.G, ch.RU, &nk);
+    if (rc || n_cells == 0) return rc;
+    // sets the kernels' dynamic-LDS limit now rather than inside a capture
+    Launch L;
+    for (const void *k : {ch.v.k_rkc, ch.v.k_rkck}) {
+        rc = plan_launch(m, ch, k, n_cells, o, true, nk, &L);
+        if (rc) return rc;
+    }
+    return RKC_OK;
+}
+
+int mech_species(const rkc_mech *m) { return m->nS; }
+int mech_device(const rkc_mech *m) { return m->device; }
+
+void fill_stats(const unsigned long long *agg, const LaunchInfo &li, rkc_stats *stats) {
+    stats->n_rhs = (int64_t)agg[0];
+    stats->n_steps = (int64_t)agg[1];
+    stats->n_reject = (int64_t)agg[2];
+    stats->n_sigma = (int64_t)agg[3];
+    stats->n_power_iter = (int64_t)agg[4];
+    stats->s_max_used = (int32_t)agg[5];
+    stats->n_failed = (int32_t)agg[6];
+    stats->worst_status = (int32_t)agg[7];
+    stats->lanes_per_cell = li.G;
+    stats->schedule = li.persistent ? RKC_SCHED_PERSISTENT : RKC_SCHED_PLAIN;
+    stats->grid_blocks = li.blocks;
+    stats->block_threads = li.threads;
+    stats->lds_bytes = (int32_t)li.lds;
+    stats->n_rhs_slots = (int64_t)agg[8];
+}
+
+}  // namespace rkchost
 
 extern "C" {
 
@@ -338,6 +515,7 @@ int rkc_mech_destroy(rkc_mech *m) {
     }
     if (m->agg_d) (void)hipFree(m->agg_d);
     if (m->queue_d) (void)hipFree(m->queue_d);
+    if (m->coef_d) (void)hipFree(m->coef_d);
     if (m->stage_d) (void)hipFree(m->stage_d);
     (void)hipSetDevice(dev);
     delete m;
@@ -439,12 +617,20 @@ int rkc_mech_create(const rkc_mech_desc *d, rkc_mech **out) {
         m->num_cus = prop.multiProcessorCount;
         m->max_lds = prop.sharedMemPerBlock;
         if (hipMalloc(&m->units_d, m->units_h.size() * 8) != hipSuccess ||
-            hipMalloc(&m->agg_d, 8 * sizeof(unsigned long long)) != hipSuccess ||
+            hipMalloc(&m->agg_d, AGG_N * sizeof(unsigned long long)) != hipSuccess ||
             hipMalloc(&m->queue_d, sizeof(int)) != hipSuccess)
             rc = RKC_ENOMEM;
         else if (hipMemcpy(m->units_d, m->units_h.data(), m->units_h.size() * 8,
                            hipMemcpyHostToDevice) != hipSuccess)
             rc = RKC_EDEVICE;
+        if (rc == RKC_OK) {
+            const std::vector<double> ct = coef_table();
+            if (hipMalloc(&m->coef_d, ct.size() * 8) != hipSuccess)
+                rc = RKC_ENOMEM;
+            else if (hipMemcpy(m->coef_d, ct.data(), ct.size() * 8, hipMemcpyHostToDevice) !=
+                     hipSuccess)
+                rc = RKC_EDEVICE;
+        }
     }
     if (rc != RKC_OK) {
         rkc_mech_destroy(m);
@@ -526,14 +712,8 @@ int rkc_integrate(const rkc_mech *mc, size_t n, double *T, const double *P, doub
     rkc_mech *m = const_cast<rkc_mech *>(mc);
     rkc_opts o;
     if (opts) o = *opts; else rkc_opts_default(&o);
-    if (!(dt > 0.0) || !std::isfinite(dt) || !(rtol > 0.0) || !std::isfinite(rtol) ||
-        !(atol >= 0.0) || !std::isfinite(atol))
-        return RKC_EINVAL;
-    if (o.method != RKC_METHOD_RKC && o.method != RKC_METHOD_RKCK) return RKC_EINVAL;
-    if (o.s_max < 2 || o.max_steps < 1) return RKC_EINVAL;
-    if (o.schedule < 0 || o.schedule > 2 || o.block_groups < 0 || o.grid_blocks < 0 ||
-        o.param_placement < 0 || o.param_placement > 2)
-        return RKC_EINVAL;
+    int rc = rkchost::check_integrate_args(dt, rtol, atol, o);
+    if (rc) return rc;
     if (stats) std::memset(stats, 0, sizeof(*stats));
     if (n == 0) return RKC_OK;
     if (!T || !P || !Y) return RKC_EINVAL;
@@ -541,16 +721,6 @@ int rkc_integrate(const rkc_mech *mc, size_t n, double *T, const double *P, doub
     int cur = 0;
     HIP_OK(hipGetDevice(&cur));
     if (cur != m->device) HIP_OK(hipSetDevice(m->device));
-    Choice ch;
-    int rc = choose_variant(m, o.lanes_per_cell, o.param_placement, &ch);
-    if (rc) return rc;
-    NkTables *nk = nullptr;
-    rc = ensure_tables(m, ch.v.G, ch.v.NSL * ch.v.G, ch.RU, &nk);
-    if (rc) return rc;
-    const void *kernel = o.method == RKC_METHOD_RKC ? ch.v.k_rkc : ch.v.k_rkck;
-    Launch L;
-    rc = plan_launch(m, ch, kernel, n, o, true, nk, &L);
-    if (rc) return rc;
 
     hipStream_t st = (hipStream_t)o.stream;
     const size_t nS = (size_t)m->nS;
@@ -572,26 +742,11 @@ int rkc_integrate(const rkc_mech *mc, size_t n, double *T, const double *P, doub
         HIP_OK(hipMemcpyAsync(Yd, Y, 8 * n * nS, hipMemcpyHostToDevice, st));
         Pd = Pb;
     }
-    hipLaunchKernelGGL(reset_scratch_kernel, dim3(1), dim3(64), 0, st, m->agg_d, m->queue_d);
-    HIP_OK(hipGetLastError());
-    rkcdev::Params p;
-    fill_params(m, ch, nk, &p);
-    p.n_cells = (int)n;
-    p.T = Td;
-    p.P = Pd;
-    p.Y = Yd;
-    p.dt = dt;
-    p.rtol = rtol;
-    p.atol = atol;
-    p.s_max = o.s_max;
-    p.max_steps = o.max_steps;
-    p.cell_status = sd;
-    p.cell_counters = cd;
-    p.persistent = L.persistent ? 1 : 0;
-    p.groups_total = L.blocks * L.groups_per_block;
-    void *args[] = {&p};
-    HIP_OK(hipLaunchKernel(kernel, dim3(L.blocks), dim3(L.threads), args, L.lds, st));
-    unsigned long long agg[8] = {0};
+    rkchost::LaunchInfo li;
+    rc = rkchost::enqueue_integrate(m, n, Td, Pd, Yd, dt, rtol, atol, o, sd, cd, m->agg_d,
+                                    m->queue_d, st, &li);
+    if (rc) return rc;
+    unsigned long long agg[AGG_N] = {0};
     const bool sync = !o.device_ptrs || stats;
     if (!o.device_ptrs) {
         HIP_OK(hipMemcpyAsync(T, Td, 8 * n, hipMemcpyDeviceToHost, st));
@@ -604,22 +759,215 @@ int rkc_integrate(const rkc_mech *mc, size_t n, double *T, const double *P, doub
         HIP_OK(hipMemcpyAsync(agg, m->agg_d, sizeof(agg), hipMemcpyDeviceToHost, st));
         HIP_OK(hipStreamSynchronize(st));
     }
-    if (stats) {
-        stats->n_rhs = (int64_t)agg[0];
-        stats->n_steps = (int64_t)agg[1];
-        stats->n_reject = (int64_t)agg[2];
-        stats->n_sigma = (int64_t)agg[3];
-        stats->n_power_iter = (int64_t)agg[4];
-        stats->s_max_used = (int32_t)agg[5];
-        stats->n_failed = (int32_t)agg[6];
-        stats->worst_status = (int32_t)agg[7];
-        stats->lanes_per_cell = ch.v.G;
-        stats->schedule = L.persistent ? RKC_SCHED_PERSISTENT : RKC_SCHED_PLAIN;
-        stats->grid_blocks = L.blocks;
-        stats->block_threads = L.threads;
-        stats->lds_bytes = (int32_t)L.lds;
-    }
+    if (stats) rkchost::fill_stats(agg, li, stats);
     if (sync && agg[6] > 0) return RKC_ECELLS;
+    return RKC_OK;
+}
+
+int rkc_divergence(size_t n, const int32_t *work, int32_t stride, int32_t width, double *D,
+                   const rkc_opts *opts) {
+    rkc_opts o;
+    if (opts) o = *opts; else rkc_opts_default(&o);
+    if (stride < 1 || width < 1) return RKC_EINVAL;
+    if (n == 0) return RKC_OK;
+    if (!work || !D) return RKC_EINVAL;
+    if (n > 0x7fffffff || (size_t)stride * n > ((size_t)1 << 40)) return RKC_ENOTSUP;
+    const size_t runs = (n + (size_t)width - 1) / (size_t)width;
+    hipStream_t st = (hipStream_t)o.stream;
+    const int32_t *wd = work;
+    double *Dd = D;
+    void *tmp = nullptr;
+    const size_t wbytes = 4 * ((n - 1) * (size_t)stride + 1);
+    if (!o.device_ptrs) {
+        if (hipMalloc(&tmp, (wbytes + 7) / 8 * 8 + 8 * runs) != hipSuccess) return RKC_ENOMEM;
+        wd = (const int32_t *)tmp;
+        Dd = (double *)((char *)tmp + ((wbytes + 7) / 8) * 8);
+        if (hip_failed(hipMemcpyAsync((void *)wd, work, wbytes, hipMemcpyHostToDevice, st),
+                       "hipMemcpyAsync(work)", __LINE__)) {
+            (void)hipFree(tmp);
+            return RKC_EDEVICE;
+        }
+    }
+    const int threads = 256;
+    const size_t blocks = (runs + threads - 1) / threads;
+    int stride_a = stride, width_a = width;
+    long long n_a = (long long)n;
+    void *args[] = {&wd, &stride_a, &n_a, &width_a, &Dd};
+    int rc = RKC_OK;
+    if (hip_failed(hipLaunchKernel(reinterpret_cast<const void *>(&divergence_kernel),
+                                   dim3((unsigned)blocks), dim3(threads), args, 0, st),
+                   "hipLaunchKernel(divergence_kernel)", __LINE__))
+        rc = RKC_EDEVICE;
+    if (!o.device_ptrs) {
+        if (rc == RKC_OK &&
+            (hip_failed(hipMemcpyAsync(D, Dd, 8 * runs, hipMemcpyDeviceToHost, st),
+                        "hipMemcpyAsync(D)", __LINE__) ||
+             hip_failed(hipStreamSynchronize(st), "hipStreamSynchronize", __LINE__)))
+            rc = RKC_EDEVICE;
+        (void)hipFree(tmp);
+    }
+    return rc;
+}
+
+int rkc_graph_destroy(rkc_graph *g) {
+    if (!g) return RKC_OK;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipSetDevice(g->device);
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    if (g->agg_d) (void)hipFree(g->agg_d);
+    if (g->queue_d) (void)hipFree(g->queue_d);
+    (void)hipSetDevice(dev);
+    delete g;
+    return RKC_OK;
+}
+
+int rkc_graph_create(const rkc_mech *mc, size_t n, double *T, const double *P, double *Y,
+                     double dt, double rtol, double atol, const rkc_opts *opts,
+                     int32_t *cell_status, rkc_graph **out) {
+    if (!mc || !out || !opts) return RKC_EINVAL;
+    *out = nullptr;
+    rkc_mech *m = const_cast<rkc_mech *>(mc);
+    rkc_opts o = *opts;
+    if (!o.device_ptrs) return RKC_EINVAL;
+    int rc = rkchost::check_integrate_args(dt, rtol, atol, o);
+    if (rc) return rc;
+    if (n == 0 || !T || !P || !Y) return RKC_EINVAL;
+    if (n > 0x7fffffff) return RKC_ENOTSUP;
+    int cur = 0;
+    HIP_OK(hipGetDevice(&cur));
+    if (cur != m->device) HIP_OK(hipSetDevice(m->device));
+    rkc_graph *g = new (std::nothrow) rkc_graph();
+    if (!g) return RKC_ENOMEM;
+    g->device = m->device;
+    hipStream_t cap = nullptr;
+    rkchost::LaunchInfo li;
+    if (hipMalloc(&g->agg_d, AGG_N * sizeof(unsigned long long)) != hipSuccess ||
+        hipMalloc(&g->queue_d, sizeof(int)) != hipSuccess)
+        rc = RKC_ENOMEM;
+    if (rc == RKC_OK) rc = rkchost::prepare(m, o, n);
+    if (rc == RKC_OK &&
+        hip_failed(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "hipStreamCreate",
+                   __LINE__))
+        rc = RKC_EDEVICE;
+    if (rc == RKC_OK &&
+        hip_failed(hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed), "BeginCapture",
+                   __LINE__))
+        rc = RKC_EDEVICE;
+    if (rc == RKC_OK) {
+        const int erc = rkchost::enqueue_integrate(m, n, T, P, Y, dt, rtol, atol, o, cell_status,
+                                                   o.cell_counters, g->agg_d, g->queue_d, cap,
+                                                   &li);
+        const bool end_bad = hip_failed(hipStreamEndCapture(cap, &g->graph), "EndCapture",
+                                        __LINE__);
+        rc = erc ? erc : (end_bad ? RKC_EDEVICE : RKC_OK);
+    }
+    if (rc == RKC_OK &&
+        hip_failed(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0),
+                   "hipGraphInstantiate", __LINE__))
+        rc = RKC_EDEVICE;
+    if (cap) (void)hipStreamDestroy(cap);
+    if (cur != m->device) (void)hipSetDevice(cur);
+    if (rc) {
+        rkc_graph_destroy(g);
+        return rc;
+    }
+    *out = g;
+    return RKC_OK;
+}
+
+int rkc_graph_launch(rkc_graph *g, void *stream) {
+    if (!g) return RKC_EINVAL;
+    HIP_OK(hipGraphLaunch(g->exec, (hipStream_t)stream));
+    return RKC_OK;
+}
+
+int rkc_autotune(const rkc_mech *mc, size_t n, const double *T, const double *P,
+                 const double *Y, double dt, double rtol, double atol, const rkc_opts *opts,
+                 rkc_opts *tuned, float *best_ms) {
+    if (!mc || !tuned) return RKC_EINVAL;
+    rkc_mech *m = const_cast<rkc_mech *>(mc);
+    rkc_opts o;
+    if (opts) o = *opts; else rkc_opts_default(&o);
+    int rc = rkchost::check_integrate_args(dt, rtol, atol, o);
+    if (rc) return rc;
+    if (n == 0 || !T || !P || !Y) return RKC_EINVAL;
+    if (n > 0x7fffffff) return RKC_ENOTSUP;
+    int cur = 0;
+    HIP_OK(hipGetDevice(&cur));
+    if (cur != m->device) HIP_OK(hipSetDevice(m->device));
+    Choice ch;
+    rc = choose_variant(m, o.lanes_per_cell, o.param_placement, &ch);
+    if (rc) return rc;
+    const int gmax = std::max(1, ch.v.max_threads / ch.v.G);
+    hipStream_t st = (hipStream_t)o.stream;
+    const size_t nS = (size_t)m->nS;
+    // working copies: [T0 | P | Y0 | T | Y | status]
+    const size_t bytes = 8 * n * (3 + 2 * nS) + 4 * n;
+    double *buf = nullptr;
+    if (hipMalloc(&buf, bytes) != hipSuccess) return RKC_ENOMEM;
+    double *T0 = buf, *Pd = buf + n, *Y0 = buf + 2 * n, *Tw = Y0 + n * nS, *Yw = Tw + n;
+    int32_t *sd = (int32_t *)(Yw + n * nS);
+    const hipMemcpyKind kind = o.device_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    rc = RKC_OK;
+    if (hip_failed(hipMemcpyAsync(T0, T, 8 * n, kind, st), "copy T", __LINE__) ||
+        hip_failed(hipMemcpyAsync(Pd, P, 8 * n, kind, st), "copy P", __LINE__) ||
+        hip_failed(hipMemcpyAsync(Y0, Y, 8 * n * nS, kind, st), "copy Y", __LINE__) ||
+        hip_failed(hipEventCreate(&e0), "event", __LINE__) ||
+        hip_failed(hipEventCreate(&e1), "event", __LINE__))
+        rc = RKC_EDEVICE;
+    // candidates: both schedules, workgroups of gmax, gmax/2 and gmax/4 groups
+    std::vector<rkc_opts> cand;
+    for (int sched : {RKC_SCHED_PERSISTENT, RKC_SCHED_PLAIN})
+        for (int div : {1, 2, 4}) {
+            if (div > 1 && gmax / div < 1) continue;
+            rkc_opts c = o;
+            c.device_ptrs = 1;
+            c.cell_counters = nullptr;
+            c.schedule = sched;
+            c.block_groups = std::max(1, gmax / div);
+            c.grid_blocks = 0;
+            cand.push_back(c);
+        }
+    float best = -1.0f;
+    for (size_t i = 0; rc == RKC_OK && i <= cand.size(); ++i) {
+        // i == 0 is an untimed warm-up of the first candidate (first-use tables)
+        const rkc_opts &c = cand[i == 0 ? 0 : i - 1];
+        rkchost::LaunchInfo li;
+        if (hip_failed(hipMemcpyAsync(Tw, T0, 8 * n, hipMemcpyDeviceToDevice, st), "copy", __LINE__) ||
+            hip_failed(hipMemcpyAsync(Yw, Y0, 8 * n * nS, hipMemcpyDeviceToDevice, st), "copy",
+                       __LINE__) ||
+            hip_failed(hipEventRecord(e0, st), "record", __LINE__)) {
+            rc = RKC_EDEVICE;
+            break;
+        }
+        rc = rkchost::enqueue_integrate(m, n, Tw, Pd, Yw, dt, rtol, atol, c, sd, nullptr,
+                                        m->agg_d, m->queue_d, st, &li);
+        if (rc) break;
+        float ms = 0.0f;
+        if (hip_failed(hipEventRecord(e1, st), "record", __LINE__) ||
+            hip_failed(hipEventSynchronize(e1), "sync", __LINE__) ||
+            hip_failed(hipEventElapsedTime(&ms, e0, e1), "elapsed", __LINE__)) {
+            rc = RKC_EDEVICE;
+            break;
+        }
+        if (i > 0 && (best < 0.0f || ms < best)) {
+            best = ms;
+            *tuned = o;
+            tuned->schedule = c.schedule;
+            tuned->block_groups = c.block_groups;
+            tuned->grid_blocks = 0;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(buf);
+    if (cur != m->device) (void)hipSetDevice(cur);
+    if (rc) return rc;
+    if (best_ms) *best_ms = best;
     return RKC_OK;
 }
 

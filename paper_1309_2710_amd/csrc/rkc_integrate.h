@@ -27,9 +27,12 @@ struct Counts {
     int n_rhs, n_steps, n_reject, n_sigma, s_max_used, s_hash, n_piter;
 };
 
+// Per-group aggregate statistics, kept in the group's LDS state record until
+// the kernel ends (they would otherwise hold a dozen registers for its whole
+// lifetime).
 struct Agg {
-    unsigned long long rhs = 0, steps = 0, rej = 0, sig = 0, piter = 0;
-    int smax = 0, failed = 0, worst = 0;
+    unsigned long long rhs, steps, rej, sig, piter;
+    int smax, failed, worst;
 };
 
 __device__ __forceinline__ void agg_cell(Agg &a, const Counts &c, int status) {
@@ -54,8 +57,12 @@ __device__ __forceinline__ int wmax_i(int x) {
     return x;
 }
 
-__device__ __forceinline__ void flush_agg(const Params &p, Agg a, bool leader) {
-    if (!leader) a = Agg();
+// `slots` is the number of source-term evaluations the wave issued (loop
+// iterations times groups per wave); with n_rhs it gives the fraction of
+// issued evaluations that advanced a cell.
+__device__ __forceinline__ void flush_agg(const Params &p, Agg a, bool leader,
+                                          unsigned long long slots) {
+    if (!leader) a = Agg{0, 0, 0, 0, 0, 0, 0, 0};
     const unsigned long long r = wsum_u64(a.rhs), s = wsum_u64(a.steps), j = wsum_u64(a.rej),
                              g = wsum_u64(a.sig), pi = wsum_u64(a.piter),
                              f = wsum_u64((unsigned long long)a.failed);
@@ -69,6 +76,7 @@ __device__ __forceinline__ void flush_agg(const Params &p, Agg a, bool leader) {
         atomicMax(p.agg + 5, (unsigned long long)sm);
         atomicAdd(p.agg + 6, f);
         atomicMax(p.agg + 7, (unsigned long long)w);
+        atomicAdd(p.agg + 8, slots);
     }
 }
 
@@ -130,19 +138,21 @@ __device__ __forceinline__ void store_counts(const Params &p, int cell, int g, c
 template <int G, int NSL>
 __device__ __forceinline__ double rms_norm(const double (&d)[NSL], const double (&ya)[NSL],
                                            const double (&yb)[NSL], double rtol, double atol,
-                                           int g, int N) {
+                                           int g, int N, double invN) {
     double s2 = 0.0;
 #pragma unroll
     for (int s = 0; s < NSL; ++s) {
         const int k = s * G + g;
         if (k < N) {
             const double m = fmax(fabs(ya[s]), fabs(yb[s]));
-            const double q = d[s] / (atol + rtol * m);
+            const double w = atol + rtol * m;
+            // d / w; a zero weight (atol = 0 and y = 0) gives a non-finite norm
+            const double q = w > 0.0 ? d[s] * rcp_nr(w) : d[s] / w;
             s2 += q * q;
         }
     }
     s2 = gsum<G>(s2);
-    return sqrt(s2 / (double)N);
+    return sqrt(s2 * invN);
 }
 
 #define RKC_KERNEL_PROLOGUE                                                                  \
@@ -160,8 +170,7 @@ __device__ __forceinline__ double rms_norm(const double (&d)[NSL], const double 
     const int N = p.N;                                                                       \
     const double u_round = 0x1p-53;                                                          \
     const double t_end = p.dt;                                                               \
-    const double h_min = 10.0 * u_round * t_end;                                             \
-    Agg agg;
+    const double h_min = 10.0 * u_round * t_end;
 
 // Per-group control state of the RKC machine, kept in LDS: it is only used
 // between source-term evaluations, so it does not occupy registers while the
@@ -169,8 +178,9 @@ __device__ __forceinline__ double rms_norm(const double (&d)[NSL], const double 
 struct RkcState {
     double t, h, sigma, sigma_prev, delta, ht, h_prev, lerr_prev, P10, invP10;
     double w0, w1, Tm1, Tm2, Tpm1, Tpm2, Tppm1, Tppm2, bm1, ibm1, ibm2;
-    int cell, phase, k_pow, s, j, last, need_sigma, since_sigma, predictive, after;
+    int cell, phase, k_pow, s, j, last, need_sigma, since_sigma, predictive, after, tab;
     Counts c;
+    Agg agg;
 };
 static_assert(sizeof(RkcState) <= STATE_BYTES, "RKC state exceeds its LDS slot");
 
@@ -192,6 +202,7 @@ __global__ __launch_bounds__((Occ<RUC, NSL>::threads), (Occ<RUC, NSL>::waves)) v
         z[i] = (i == 0 && g == 0) ? 1000.0 : 0.0;
     }
     S.P10 = 1e6;
+    S.agg = Agg{0, 0, 0, 0, 0, 0, 0, 0};
     S.invP10 = 1e-6;
 
     // Take the next valid cell starting at `first` (cells with bad input are
@@ -214,7 +225,7 @@ __global__ __launch_bounds__((Occ<RUC, NSL>::threads), (Occ<RUC, NSL>::waves)) v
             }
             Counts zc{0, 0, 0, 0, 0, 0, 0};
             store_counts(p, cell, g, zc, ST_BADINPUT);
-            agg_cell(agg, zc, ST_BADINPUT);
+            agg_cell(S.agg, zc, ST_BADINPUT);
             cell = next_cell<G>(p, g);
         }
         S.cell = -1;
@@ -222,14 +233,34 @@ __global__ __launch_bounds__((Occ<RUC, NSL>::threads), (Occ<RUC, NSL>::waves)) v
 
     acquire(blockIdx.x * groups + gib);
 
+    unsigned iters = 0;
     for (;;) {
+        if (!__any(S.cell >= 0)) break;   // a wave whose groups hold no cell issues nothing
+        ++iters;
         rhs_eval<G, NSL, RUC>(z, S.P10, S.invP10, fz, L, ur, g, N, p.RU, p.NSEG, p.SEGL);
         if (S.cell >= 0) {
             Counts c = S.c;
             c.n_rhs += 1;
             int act = ACT_NONE, fin = ST_OK;
             const int phase = S.phase;
-            if (phase == PH_STAGE) {
+            if (phase == PH_STAGE && S.tab) {
+                // (E:rkcj) with the tabulated coefficients of (s, j)
+                const int j = S.j;
+                const double4 cf =
+                    *reinterpret_cast<const double4 *>(p.coef + 4 * (coef_offset(S.s) + j - 1));
+                const double h = S.h;
+                const double c0 = 1.0 - cf.x - cf.y, ch1 = cf.z * h, ch2 = cf.w * h;
+#pragma unroll
+                for (int i = 0; i < NSL; ++i) {
+                    const double wj = c0 * y[i] + cf.x * wm1[i] + cf.y * wm2[i] + ch1 * fz[i] +
+                                      ch2 * f0[i];
+                    wm2[i] = wm1[i];
+                    wm1[i] = wj;
+                    z[i] = wj;
+                }
+                if (j == S.s) S.phase = PH_ERR;
+                else S.j = j + 1;
+            } else if (phase == PH_STAGE) {
                 // (E:rkcj) with the coefficient recurrences advanced one stage;
                 // 1/b_{j-1} and 1/b_{j-2} are carried, so a stage needs two
                 // divisions (b_j and 1/b_j)
@@ -264,7 +295,7 @@ __global__ __launch_bounds__((Occ<RUC, NSL>::threads), (Occ<RUC, NSL>::waves)) v
 #pragma unroll
                 for (int i = 0; i < NSL; ++i)
                     d[i] = 0.8 * (y[i] - wm1[i]) + 0.4 * h * (f0[i] + fz[i]);
-                const double err = rms_norm<G, NSL>(d, y, wm1, p.rtol, p.atol, g, N);
+                const double err = rms_norm<G, NSL>(d, y, wm1, p.rtol, p.atol, g, N, p.invN);
                 if (err <= 1.0) {
                     c.n_steps += 1;
 #pragma unroll
@@ -356,7 +387,7 @@ __global__ __launch_bounds__((Occ<RUC, NSL>::threads), (Occ<RUC, NSL>::waves)) v
                 double d[NSL];
 #pragma unroll
                 for (int i = 0; i < NSL; ++i) d[i] = ht * (fz[i] - f0[i]);
-                const double e0 = rms_norm<G, NSL>(d, y, y, p.rtol, p.atol, g, N);
+                const double e0 = rms_norm<G, NSL>(d, y, y, p.rtol, p.atol, g, N, p.invN);
                 if (!isfinite(e0)) {
                     act = ACT_FINISH;
                     fin = ST_NONFINITE;
@@ -433,25 +464,34 @@ __global__ __launch_bounds__((Occ<RUC, NSL>::threads), (Occ<RUC, NSL>::waves)) v
                 }
                 c.s_hash = (int)((unsigned)c.s_hash * 31u + (unsigned)s);
                 c.s_max_used = max(c.s_max_used, s);
-                // Chebyshev values at w0 = 1 + kappa/s^2 up to degree s, for w1 = T'_s/T''_s
-                const double w0 = 1.0 + KAPPA / ((double)s * (double)s);
-                double T0 = 1.0, T1 = w0, P0 = 0.0, P1 = 1.0, Q0 = 0.0, Q1 = 0.0;
-                double P2 = 0.0, Q2 = 0.0;
-                for (int jj = 2; jj <= s; ++jj) {
-                    const double Tn = 2.0 * w0 * T1 - T0;
-                    const double Pn = 2.0 * w0 * P1 - P0 + 2.0 * T1;
-                    const double Qn = 2.0 * w0 * Q1 - Q0 + 4.0 * P1;
-                    if (jj == 2) { P2 = Pn; Q2 = Qn; }
-                    T0 = T1; T1 = Tn; P0 = P1; P1 = Pn; Q0 = Q1; Q1 = Qn;
+                double mu_t1;
+                if (s <= p.coef_smax) {
+                    mu_t1 = p.coef[4 * coef_offset(s)];
+                    S.tab = 1;
+                } else {
+                    // Chebyshev values at w0 = 1 + kappa/s^2 up to degree s, for
+                    // w1 = T'_s/T''_s; the stages then advance the recurrences
+                    S.tab = 0;
+                    const double w0 = 1.0 + KAPPA / ((double)s * (double)s);
+                    double T0 = 1.0, T1 = w0, P0 = 0.0, P1 = 1.0, Q0 = 0.0, Q1 = 0.0;
+                    double P2 = 0.0, Q2 = 0.0;
+                    for (int jj = 2; jj <= s; ++jj) {
+                        const double Tn = 2.0 * w0 * T1 - T0;
+                        const double Pn = 2.0 * w0 * P1 - P0 + 2.0 * T1;
+                        const double Qn = 2.0 * w0 * Q1 - Q0 + 4.0 * P1;
+                        if (jj == 2) { P2 = Pn; Q2 = Qn; }
+                        T0 = T1; T1 = Tn; P0 = P1; P1 = Pn; Q0 = Q1; Q1 = Qn;
+                    }
+                    const double w1 = P1 / Q1;
+                    const double b1 = 1.0 / w0;
+                    const double b2 = Q2 / (P2 * P2);
+                    S.w0 = w0; S.w1 = w1;
+                    S.Tm1 = w0; S.Tm2 = 1.0; S.Tpm1 = 1.0; S.Tpm2 = 0.0; S.Tppm1 = 0.0;
+                    S.Tppm2 = 0.0;
+                    S.bm1 = b1; S.ibm1 = w0; S.ibm2 = 1.0 / b2;   // b_1 = 1/w0, b_0 = b_2
+                    mu_t1 = b1 * w1;
                 }
-                const double w1 = P1 / Q1;
-                const double b1 = 1.0 / w0;
-                const double b2 = Q2 / (P2 * P2);
-                S.w0 = w0; S.w1 = w1;
-                S.Tm1 = w0; S.Tm2 = 1.0; S.Tpm1 = 1.0; S.Tpm2 = 0.0; S.Tppm1 = 0.0; S.Tppm2 = 0.0;
-                S.bm1 = b1; S.ibm1 = w0; S.ibm2 = 1.0 / b2;   // b_1 = 1/w0, b_0 = b_2
                 S.h = h; S.last = last; S.s = s; S.j = 2;
-                const double mu_t1 = b1 * w1;
 #pragma unroll
                 for (int i = 0; i < NSL; ++i) {
                     wm2[i] = y[i];
@@ -464,13 +504,12 @@ __global__ __launch_bounds__((Occ<RUC, NSL>::threads), (Occ<RUC, NSL>::waves)) v
             if (act == ACT_FINISH) {
                 store_state<G, NSL>(p, S.cell, g, y);
                 store_counts(p, S.cell, g, c, fin);
-                agg_cell(agg, c, fin);
+                agg_cell(S.agg, c, fin);
                 acquire(next_cell<G>(p, g));
             }
         }
-        if (!__any(S.cell >= 0)) break;
     }
-    flush_agg(p, agg, g == 0);
+    flush_agg(p, S.agg, g == 0, (unsigned long long)iters * (64 / G));
 }
 
 // ------------------------------------------------------------------ RKCK
@@ -505,6 +544,7 @@ struct RkckState {
     double t, h, P10, invP10;
     int cell, phase, last;
     Counts c;
+    Agg agg;
 };
 static_assert(sizeof(RkckState) <= STATE_BYTES, "RKCK state exceeds its LDS slot");
 
@@ -520,6 +560,7 @@ __global__ __launch_bounds__((Occ<RUC, NSL>::threads), (Occ<RUC, NSL>::waves)) v
         z[i] = (i == 0 && g == 0) ? 1000.0 : 0.0;
     }
     S.P10 = 1e6;
+    S.agg = Agg{0, 0, 0, 0, 0, 0, 0, 0};
     S.invP10 = 1e-6;
 
     auto acquire = [&](int first) {
@@ -542,7 +583,7 @@ __global__ __launch_bounds__((Occ<RUC, NSL>::threads), (Occ<RUC, NSL>::waves)) v
             }
             Counts zc{0, 0, 0, 0, 0, 0, 0};
             store_counts(p, cell, g, zc, ST_BADINPUT);
-            agg_cell(agg, zc, ST_BADINPUT);
+            agg_cell(S.agg, zc, ST_BADINPUT);
             cell = next_cell<G>(p, g);
         }
         S.cell = -1;
@@ -550,7 +591,10 @@ __global__ __launch_bounds__((Occ<RUC, NSL>::threads), (Occ<RUC, NSL>::waves)) v
 
     acquire(blockIdx.x * groups + gib);
 
+    unsigned iters = 0;
     for (;;) {
+        if (!__any(S.cell >= 0)) break;   // a wave whose groups hold no cell issues nothing
+        ++iters;
         rhs_eval<G, NSL, RUC>(z, S.P10, S.invP10, fz, L, ur, g, N, p.RU, p.NSEG, p.SEGL);
         if (S.cell >= 0) {
             Counts c = S.c;
@@ -655,13 +699,12 @@ __global__ __launch_bounds__((Occ<RUC, NSL>::threads), (Occ<RUC, NSL>::waves)) v
             if (fin >= 0) {
                 store_state<G, NSL>(p, S.cell, g, y);
                 store_counts(p, S.cell, g, c, fin);
-                agg_cell(agg, c, fin);
+                agg_cell(S.agg, c, fin);
                 acquire(next_cell<G>(p, g));
             }
         }
-        if (!__any(S.cell >= 0)) break;
     }
-    flush_agg(p, agg, g == 0);
+    flush_agg(p, S.agg, g == 0, (unsigned long long)iters * (64 / G));
 }
 
 }  // namespace rkcdev

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include "rkc.h"
 #include "rkc_device.h"
 
 namespace rkchost {
@@ -22,6 +23,44 @@ const VariantDesc *variants_g64(int *n);
 const VariantDesc *variants_g32(int *n);
 const VariantDesc *variants_g16(int *n);
 const VariantDesc *variants_g8(int *n);
+
+// Aggregate counters per launch (n_rhs, n_steps, n_reject, n_sigma,
+// n_power_iter, s_max_used, n_failed, worst_status, issued slots; rest spare).
+constexpr int AGG_N = 16;
+
+// What one integrator launch ran (for rkc_stats).
+struct LaunchInfo {
+    int G = 0, blocks = 0, threads = 0;
+    bool persistent = false;
+    size_t lds = 0;
+};
+
+}  // namespace rkchost
+
+
+namespace rkchost {
+
+// Validate the scalar arguments and options of an integration.
+int check_integrate_args(double dt, double rtol, double atol, const rkc_opts &o);
+
+// Enqueue one integration of n cells whose arrays are device pointers on the
+// mechanism's device, with the launch's own scratch (aggregate counters
+// [16], work-queue head): launches that use distinct scratch may run
+// concurrently on different streams.  Not thread-safe for one mechanism
+// (its per-shape table cache is filled on first use).
+int enqueue_integrate(rkc_mech *m, size_t n, double *Td, const double *Pd, double *Yd, double dt,
+                      double rtol, double atol, const rkc_opts &o, int32_t *sd, int32_t *cd,
+                      unsigned long long *agg_d, int *queue_d, hipStream_t st, LaunchInfo *li);
+
+// Select the variant and build the device tables a later enqueue_integrate
+// with these options will use (so that concurrent launches only read them);
+// with n_cells > 0 also fix the kernels' launch attributes for that size.
+int prepare(rkc_mech *m, const rkc_opts &o, size_t n_cells);
+int mech_species(const rkc_mech *m);
+int mech_device(const rkc_mech *m);
+
+// Statistics of one launch from its aggregate counters ([16], see the kernels).
+void fill_stats(const unsigned long long *agg, const LaunchInfo &li, rkc_stats *stats);
 
 }  // namespace rkchost
 

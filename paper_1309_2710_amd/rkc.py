@@ -29,7 +29,11 @@ COUNTER_FIELDS = ["n_rhs", "n_steps", "n_reject", "n_sigma", "s_max_used", "s_ha
                   "n_power_iter"]
 
 EXPORTED = ["rkc_opts_default", "rkc_mech_create", "rkc_mech_destroy", "rkc_mech_info",
-            "rkc_rhs", "rkc_integrate", "rkc_strerror"]
+            "rkc_rhs", "rkc_integrate", "rkc_autotune", "rkc_divergence", "rkc_graph_create",
+            "rkc_graph_launch", "rkc_graph_destroy", "rkc_strerror"]
+SERVER_EXPORTED = ["rkc_server_opts_default", "rkc_server_create", "rkc_server_destroy",
+                   "rkc_server_register_mech", "rkc_server_submit", "rkc_server_poll",
+                   "rkc_server_wait", "rkc_server_get_stats", "rkc_server_reset_stats"]
 
 
 class MechDesc(ct.Structure):
@@ -53,7 +57,25 @@ class Stats(ct.Structure):
                 ("s_max_used", ct.c_int32), ("n_failed", ct.c_int32),
                 ("worst_status", ct.c_int32), ("lanes_per_cell", ct.c_int32),
                 ("schedule", ct.c_int32), ("grid_blocks", ct.c_int32),
-                ("block_threads", ct.c_int32), ("lds_bytes", ct.c_int32)]
+                ("block_threads", ct.c_int32), ("lds_bytes", ct.c_int32),
+                ("n_rhs_slots", ct.c_int64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class ServerOpts(ct.Structure):
+    _fields_ = [("budget_bytes", ct.c_size_t), ("n_streams", ct.c_int32),
+                ("max_batch_cells", ct.c_int32), ("lanes_per_cell", ct.c_int32),
+                ("param_placement", ct.c_int32)]
+
+
+class ServerStats(ct.Structure):
+    _fields_ = [("submitted", ct.c_int64), ("completed", ct.c_int64),
+                ("failed_requests", ct.c_int64), ("launches", ct.c_int64), ("cells", ct.c_int64),
+                ("n_rhs", ct.c_int64), ("peak_bytes", ct.c_int64), ("peak_queue", ct.c_int64),
+                ("mean_ms", ct.c_double), ("p50_ms", ct.c_double), ("p99_ms", ct.c_double),
+                ("max_ms", ct.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -92,6 +114,29 @@ def lib():
         L.rkc_integrate.argtypes = [ct.c_void_p, ct.c_size_t, ct.c_void_p, ct.c_void_p,
                                     ct.c_void_p, ct.c_double, ct.c_double, ct.c_double,
                                     ct.POINTER(Opts), ct.c_void_p, ct.POINTER(Stats)]
+        L.rkc_divergence.argtypes = [ct.c_size_t, ct.c_void_p, ct.c_int32, ct.c_int32,
+                                     ct.c_void_p, ct.POINTER(Opts)]
+        L.rkc_autotune.argtypes = [ct.c_void_p, ct.c_size_t, ct.c_void_p, ct.c_void_p,
+                                    ct.c_void_p, ct.c_double, ct.c_double, ct.c_double,
+                                    ct.POINTER(Opts), ct.POINTER(Opts), ct.POINTER(ct.c_float)]
+        L.rkc_graph_create.argtypes = [ct.c_void_p, ct.c_size_t, ct.c_void_p, ct.c_void_p,
+                                        ct.c_void_p, ct.c_double, ct.c_double, ct.c_double,
+                                        ct.POINTER(Opts), ct.c_void_p, ct.POINTER(ct.c_void_p)]
+        L.rkc_graph_launch.argtypes = [ct.c_void_p, ct.c_void_p]
+        L.rkc_graph_destroy.argtypes = [ct.c_void_p]
+        L.rkc_server_opts_default.argtypes = [ct.POINTER(ServerOpts)]
+        L.rkc_server_create.argtypes = [ct.POINTER(ServerOpts), ct.POINTER(ct.c_void_p)]
+        L.rkc_server_destroy.argtypes = [ct.c_void_p]
+        L.rkc_server_register_mech.argtypes = [ct.c_void_p, ct.POINTER(MechDesc),
+                                               ct.POINTER(ct.c_int32)]
+        L.rkc_server_submit.argtypes = [ct.c_void_p, ct.c_int32, ct.c_size_t, ct.c_void_p,
+                                        ct.c_void_p, ct.c_void_p, ct.c_double, ct.c_double,
+                                        ct.c_double, ct.c_int32, ct.c_void_p,
+                                        ct.POINTER(ct.c_uint64)]
+        L.rkc_server_poll.argtypes = [ct.c_void_p, ct.c_uint64, ct.POINTER(ct.c_int32)]
+        L.rkc_server_wait.argtypes = [ct.c_void_p, ct.c_uint64, ct.POINTER(ct.c_int32)]
+        L.rkc_server_get_stats.argtypes = [ct.c_void_p, ct.POINTER(ServerStats)]
+        L.rkc_server_reset_stats.argtypes = [ct.c_void_p]
         L.rkc_strerror.restype = ct.c_char_p
         L.rkc_strerror.argtypes = [ct.c_int]
         _lib = L
@@ -109,26 +154,33 @@ def _np_ptr(a):
     return a.ctypes.data_as(ct.c_void_p)
 
 
+def _mech_desc(mech):
+    """(rkc_mech_desc, arrays it points into) for a mechanism dict."""
+    nS, nR = int(mech["n_species"]), int(mech["n_reactions"])
+    keep = {
+        "W": np.ascontiguousarray(mech["W"], np.float64),
+        "nasa_low": np.ascontiguousarray(mech["nasa_low"], np.float64),
+        "nasa_high": np.ascontiguousarray(mech["nasa_high"], np.float64),
+        "T_mid": np.ascontiguousarray(mech["T_mid"], np.float64),
+        "reac": np.ascontiguousarray(mech["reac"], np.int32),
+        "prod": np.ascontiguousarray(mech["prod"], np.int32),
+        "A": np.ascontiguousarray(mech["A"], np.float64),
+        "beta": np.ascontiguousarray(mech["beta"], np.float64),
+        "Ea": np.ascontiguousarray(mech["Ea"], np.float64),
+    }
+    d = MechDesc(nS, nR, *[_np_ptr(keep[k]) for k in
+                           ["W", "nasa_low", "nasa_high", "T_mid", "reac", "prod", "A",
+                            "beta", "Ea"]])
+    return d, keep
+
+
 class Mechanism:
     """A mechanism uploaded to the current HIP device (rkc_mech_create)."""
 
     def __init__(self, mech):
         L = lib()
         nS, nR = int(mech["n_species"]), int(mech["n_reactions"])
-        keep = {
-            "W": np.ascontiguousarray(mech["W"], np.float64),
-            "nasa_low": np.ascontiguousarray(mech["nasa_low"], np.float64),
-            "nasa_high": np.ascontiguousarray(mech["nasa_high"], np.float64),
-            "T_mid": np.ascontiguousarray(mech["T_mid"], np.float64),
-            "reac": np.ascontiguousarray(mech["reac"], np.int32),
-            "prod": np.ascontiguousarray(mech["prod"], np.int32),
-            "A": np.ascontiguousarray(mech["A"], np.float64),
-            "beta": np.ascontiguousarray(mech["beta"], np.float64),
-            "Ea": np.ascontiguousarray(mech["Ea"], np.float64),
-        }
-        d = MechDesc(nS, nR, *[_np_ptr(keep[k]) for k in
-                               ["W", "nasa_low", "nasa_high", "T_mid", "reac", "prod", "A",
-                                "beta", "Ea"]])
+        d, keep = _mech_desc(mech)
         h = ct.c_void_p()
         rc = L.rkc_mech_create(ct.byref(d), ct.byref(h))
         if rc != OK:
@@ -241,6 +293,98 @@ def integrate(mech, T, P, Y, dt, rtol=1e-6, atol=1e-10, method=RKC, lanes_per_ce
     return out
 
 
+def autotune(mech, T, P, Y, dt, rtol=1e-6, atol=1e-10, method=RKC, lanes_per_cell=0,
+             param_placement=PARAMS_AUTO):
+    """rkc_autotune on a sample of cells (numpy or torch GPU arrays, left
+    unchanged).  Returns (dict of integrate() keyword arguments, best ms)."""
+    dev = _is_torch(T)
+    if dev:
+        ptrs = [ct.c_void_p(a.data_ptr()) for a in (T, P, Y)]
+        o = make_opts(method, lanes_per_cell=lanes_per_cell, device_ptrs=True,
+                      stream=_stream_handle(None, [T]), param_placement=param_placement)
+    else:
+        keep = [np.ascontiguousarray(a, np.float64) for a in (T, P, Y)]
+        ptrs = [_np_ptr(a) for a in keep]
+        o = make_opts(method, lanes_per_cell=lanes_per_cell, param_placement=param_placement)
+    t = Opts()
+    ms = ct.c_float()
+    rc = lib().rkc_autotune(mech.handle, int(T.shape[0]), *ptrs, float(dt), float(rtol),
+                            float(atol), ct.byref(o), ct.byref(t), ct.byref(ms))
+    if rc != OK:
+        raise RkcError(rc, "rkc_autotune")
+    return {"schedule": t.schedule, "block_groups": t.block_groups,
+            "grid_blocks": t.grid_blocks}, ms.value
+
+
+class Graph:
+    """One recorded global step over device arrays (rkc_graph_create);
+    launch() replays it on a stream.  The tensors must outlive the graph."""
+
+    def __init__(self, mech, T, P, Y, dt, rtol=1e-6, atol=1e-10, method=RKC, lanes_per_cell=0,
+                 schedule=SCHED_AUTO, block_groups=0, grid_blocks=0, s_max=1000,
+                 max_steps=1000000, status=None, param_placement=PARAMS_AUTO):
+        import torch
+        for a in (T, P, Y):
+            assert a.is_cuda and a.dtype == torch.float64 and a.is_contiguous()
+        o = make_opts(method, s_max, max_steps, lanes_per_cell, schedule, block_groups,
+                      grid_blocks, True, None, None, param_placement)
+        h = ct.c_void_p()
+        rc = lib().rkc_graph_create(mech.handle, int(T.shape[0]), ct.c_void_p(T.data_ptr()),
+                                    ct.c_void_p(P.data_ptr()), ct.c_void_p(Y.data_ptr()),
+                                    float(dt), float(rtol), float(atol), ct.byref(o),
+                                    ct.c_void_p(status.data_ptr()) if status is not None else None,
+                                    ct.byref(h))
+        if rc != OK:
+            raise RkcError(rc, "rkc_graph_create")
+        self._h = h
+        self._keep = (mech, T, P, Y, status)
+
+    def launch(self, stream=None):
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream()
+        rc = lib().rkc_graph_launch(self._h, ct.c_void_p(s.cuda_stream))
+        if rc != OK:
+            raise RkcError(rc, "rkc_graph_launch")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().rkc_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def divergence(work, width=32, stride=1, stream=None):
+    """Divergence measure D (Sec. 3.2) of runs of `width` consecutive cells.
+
+    work: per-cell work counts, int32, numpy (host) or torch GPU tensor; a 2-D
+    array of counters is read column 0 with its row stride.  Returns D as the
+    same kind of array."""
+    L = lib()
+    n = int(work.shape[0])
+    runs = (n + width - 1) // width
+    if _is_torch(work):
+        import torch
+        assert work.is_cuda and work.dtype == torch.int32 and work.is_contiguous()
+        st = int(work.stride(0)) if work.dim() == 2 else 1
+        D = torch.empty(runs, dtype=torch.float64, device=work.device)
+        o = make_opts(device_ptrs=True, stream=_stream_handle(stream, [work]))
+        rc = L.rkc_divergence(n, ct.c_void_p(work.data_ptr()), st, int(width),
+                              ct.c_void_p(D.data_ptr()), ct.byref(o))
+    else:
+        w = np.ascontiguousarray(work, np.int32)
+        st = int(w.strides[0] // 4) if w.ndim == 2 else 1
+        D = np.empty(runs, np.float64)
+        rc = L.rkc_divergence(n, _np_ptr(w), st, int(width), _np_ptr(D), None)
+    if rc != OK:
+        raise RkcError(rc, "rkc_divergence")
+    return D
+
+
 def rhs(mech, T, P, Y, lanes_per_cell=0, stream=None):
     """Source term f [n][nS+1] (column 0 = dT/dt) for numpy or torch GPU inputs."""
     L = lib()
@@ -262,3 +406,92 @@ def rhs(mech, T, P, Y, lanes_per_cell=0, stream=None):
     if rc != OK:
         raise RkcError(rc, "rkc_rhs")
     return f
+
+
+class Server:
+    """Integration server (include/rkc_server.h) on the current HIP device.
+
+    submit() takes numpy host arrays, which must stay alive and untouched
+    until wait() returns for the request (the object keeps references)."""
+
+    def __init__(self, budget_bytes=1 << 30, n_streams=4, max_batch_cells=1 << 20,
+                 lanes_per_cell=0, param_placement=PARAMS_AUTO):
+        L = lib()
+        o = ServerOpts()
+        L.rkc_server_opts_default(ct.byref(o))
+        o.budget_bytes = int(budget_bytes)
+        o.n_streams = int(n_streams)
+        o.max_batch_cells = int(max_batch_cells)
+        o.lanes_per_cell = int(lanes_per_cell)
+        o.param_placement = int(param_placement)
+        h = ct.c_void_p()
+        rc = L.rkc_server_create(ct.byref(o), ct.byref(h))
+        if rc != OK:
+            raise RkcError(rc, "rkc_server_create")
+        self._h = h
+        self._live = {}
+        self._nS = []
+
+    def register(self, mech):
+        d, keep = _mech_desc(mech)
+        mid = ct.c_int32()
+        rc = lib().rkc_server_register_mech(self._h, ct.byref(d), ct.byref(mid))
+        if rc != OK:
+            raise RkcError(rc, "rkc_server_register_mech")
+        self._nS.append(int(mech["n_species"]))
+        return mid.value
+
+    def submit(self, mech_id, T, P, Y, dt, rtol=1e-6, atol=1e-10, method=RKC, status=None):
+        for a in (T, P, Y):
+            assert isinstance(a, np.ndarray) and a.dtype == np.float64 and a.flags.c_contiguous
+        n = int(T.shape[0])
+        assert Y.shape == (n, self._nS[mech_id])
+        if status is not None:
+            assert status.dtype == np.int32 and status.shape == (n,)
+        rid = ct.c_uint64()
+        rc = lib().rkc_server_submit(self._h, int(mech_id), n, _np_ptr(T), _np_ptr(P), _np_ptr(Y),
+                                     float(dt), float(rtol), float(atol), int(method),
+                                     _np_ptr(status) if status is not None else None,
+                                     ct.byref(rid))
+        if rc != OK:
+            raise RkcError(rc, "rkc_server_submit")
+        self._live[rid.value] = (T, P, Y, status)
+        return rid.value
+
+    def poll(self, rid):
+        d = ct.c_int32()
+        rc = lib().rkc_server_poll(self._h, rid, ct.byref(d))
+        if rc != OK:
+            raise RkcError(rc, "rkc_server_poll")
+        return bool(d.value)
+
+    def wait(self, rid):
+        """(rc, n_failed); rc is OK or ECELLS (other codes raise)."""
+        nf = ct.c_int32()
+        rc = lib().rkc_server_wait(self._h, rid, ct.byref(nf))
+        self._live.pop(rid, None)
+        if rc not in (OK, ECELLS):
+            raise RkcError(rc, "rkc_server_wait")
+        return rc, nf.value
+
+    def stats(self):
+        s = ServerStats()
+        rc = lib().rkc_server_get_stats(self._h, ct.byref(s))
+        if rc != OK:
+            raise RkcError(rc, "rkc_server_get_stats")
+        return s.as_dict()
+
+    def reset_stats(self):
+        lib().rkc_server_reset_stats(self._h)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().rkc_server_destroy(self._h)
+            self._h = None
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
