@@ -29,7 +29,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6        # MI355X FP64 vector: 256 CU x 128 flop/clk x 2.4 GHz
-EXP_FLOPS = 27                 # FP64 arithmetic of one device exp: 13 FMA + 1 MUL
+EXP_FLOPS = 27                 # FP64 arithmetic of one device exp: 1 MUL + 2 FMA + 11 FMA
 METRIC = "cell-ODEs integrated per sec over dt (53sp/634rx, FP64); p99 batch latency"
 
 
@@ -254,7 +254,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "%s: RKC, %s" % (cfg, c["label"]), "n_cells": n,
+        "config": {"workload": "RKC, %s" % c["label"], "n_cells": n,
                    "n_species": mech["n_species"], "n_reactions": mech["n_reactions"],
                    "dt": c["dt"], "rtol": c["rtol"], "atol": c["atol"],
                    "lanes_per_cell": census[0]["lanes_per_cell"],
@@ -407,7 +407,7 @@ def serve(args):
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "c5: %d requests, Poisson %.0f req/s over %.2f s, 2^U(10,16) "
+        "config": {"workload": "mixed 13/53-species requests: %d, Poisson %.0f req/s over %.2f s, 2^U(10,16) "
                                "cells, 13/53 species, dt 1e-6/1e-5" % (len(trace), args.serve_rate,
                                                                         span),
                    "cells": cells, "n_streams": args.serve_streams},

@@ -217,26 +217,26 @@ __device__ __forceinline__ double unpack_c(const double *C, uint32_t id, int s) 
 }
 
 // exp(x) for |x| < 1e9: Cody & Waite reduction x = n ln2 + r, |r| <= ln2/2,
-// with ln2 split into its double rounding and the remainder, then the Taylor
-// polynomial of exp(r) through r^13 (truncation < 2^-57 relative) by Horner,
-// scaled by 2^n.  Underflows to exactly 0 below about -745; NaN propagates.
-// Within about one ulp; written so every Horner step is one FMA.
+// with ln2 split into its double rounding and the remainder, then
+// exp(r) = 1 + r + r^2 q(r) with q a degree-9 Chebyshev fit of
+// (exp(r) - 1 - r)/r^2 on the reduced interval (relative error below 1.6e-17;
+// fit_exp_poly.py prints the coefficients), by Horner, scaled by 2^n.
+// Underflows to exactly 0 below about -745; NaN propagates.  Within about one
+// ulp; written so every Horner step is one FMA.
 __device__ __forceinline__ double exp_cw(double x) {
     const double n = __builtin_rint(x * 0x1.71547652b82fep+0);
     const double r = __builtin_fma(-n, 0x1.abc9e3b39803fp-56,
                                    __builtin_fma(-n, 0x1.62e42fefa39efp-1, x));
-    double q = 1.0 / 6227020800.0;
-    q = __builtin_fma(q, r, 1.0 / 479001600.0);
-    q = __builtin_fma(q, r, 1.0 / 39916800.0);
-    q = __builtin_fma(q, r, 1.0 / 3628800.0);
-    q = __builtin_fma(q, r, 1.0 / 362880.0);
-    q = __builtin_fma(q, r, 1.0 / 40320.0);
-    q = __builtin_fma(q, r, 1.0 / 5040.0);
-    q = __builtin_fma(q, r, 1.0 / 720.0);
-    q = __builtin_fma(q, r, 1.0 / 120.0);
-    q = __builtin_fma(q, r, 1.0 / 24.0);
-    q = __builtin_fma(q, r, 1.0 / 6.0);
-    q = __builtin_fma(q, r, 0.5);
+    double q = 2.5100375832561234e-08;
+    q = __builtin_fma(q, r, 2.7620075879983367e-07);
+    q = __builtin_fma(q, r, 2.7557268480310024e-06);
+    q = __builtin_fma(q, r, 2.4801521322368692e-05);
+    q = __builtin_fma(q, r, 0.00019841269863040545);
+    q = __builtin_fma(q, r, 0.0013888888917196719);
+    q = __builtin_fma(q, r, 0.008333333333330065);
+    q = __builtin_fma(q, r, 0.041666666666624164);
+    q = __builtin_fma(q, r, 0.16666666666666669);
+    q = __builtin_fma(q, r, 0.5000000000000001);
     q = __builtin_fma(q, r, 1.0);
     q = __builtin_fma(q, r, 1.0);
     return __builtin_ldexp(q, (int)n);
@@ -349,8 +349,10 @@ __device__ __forceinline__ void rhs_eval(const double (&z)[NSL], double P10, dou
     } else {
         for (int r = 0; r < RU; ++r) {
             const int p = r * G + g;
-            const double2 *u = reinterpret_cast<const double2 *>(L.units + (size_t)p * UNIT_DOUBLES);
-            const double2 u0 = u[0], u1 = u[1], u2 = u[2], u3 = u[3];
+            // LDS copy is lane-interleaved: 16-byte piece q of unit r * G + g at
+            // double2 index (4 r + q) G + g, so a wave's reads are contiguous
+            const double2 *u = reinterpret_cast<const double2 *>(L.units) + (size_t)(4 * r) * G + g;
+            const double2 u0 = u[0], u1 = u[G], u2 = u[2 * G], u3 = u[3 * G];
             const uint64_t a = __double_as_longlong(u3.x), b = __double_as_longlong(u3.y);
             const double kf = exp_cw(u0.x + u0.y * lnT - u1.x * invT);
             const double kr = exp_cw(u1.y + u2.x * lnT - u2.y * invT);
@@ -410,7 +412,13 @@ __device__ __forceinline__ void stage_tables(const Params &p, int G, double *spe
     for (int i = tid; i < NFIELD * p.NK; i += nt) spec_l[i] = p.tab.spec[i];
     for (int i = tid; i < p.NSEG * (p.SEGL / 2) * G; i += nt) gather_l[i] = p.tab.gather[i];
     for (int i = tid; i <= 2 * p.NK; i += nt) ps_l[i] = p.tab.ps[i];
-    for (int i = tid; i < n_units_l * UNIT_DOUBLES; i += nt) units_l[i] = p.tab.units[i];
+    // unit records, lane-interleaved in 16-byte pieces (see rhs_eval)
+    const double2 *ug = reinterpret_cast<const double2 *>(p.tab.units);
+    double2 *ul = reinterpret_cast<double2 *>(units_l);
+    for (int i = tid; i < n_units_l * (UNIT_DOUBLES / 2); i += nt) {
+        const int unit = i / (UNIT_DOUBLES / 2), q = i % (UNIT_DOUBLES / 2);
+        ul[((unit / G) * (UNIT_DOUBLES / 2) + q) * G + unit % G] = ug[i];
+    }
 }
 
 template <int RUC>

@@ -216,6 +216,14 @@ def _is_torch(x):
     return type(x).__module__.startswith("torch")
 
 
+def _check_shapes(mech, n, P, Y):
+    """The C ABI takes bare pointers: check here that P is [n] and Y is
+    [n][n_species] of this mechanism."""
+    if tuple(P.shape) != (n,) or tuple(Y.shape) != (n, mech.n_species):
+        raise ValueError("shape mismatch: T [%d], P %s, Y %s for a mechanism with %d species"
+                         % (n, tuple(P.shape), tuple(Y.shape), mech.n_species))
+
+
 def make_opts(method=RKC, s_max=1000, max_steps=1000000, lanes_per_cell=0,
               schedule=SCHED_AUTO, block_groups=0, grid_blocks=0, device_ptrs=False,
               stream=None, cell_counters=None, param_placement=PARAMS_AUTO):
@@ -256,6 +264,7 @@ def integrate(mech, T, P, Y, dt, rtol=1e-6, atol=1e-10, method=RKC, lanes_per_ce
     L = lib()
     dev = _is_torch(T)
     n = int(T.shape[0])
+    _check_shapes(mech, n, P, Y)
     out = {}
     if dev:
         import torch
@@ -389,6 +398,7 @@ def rhs(mech, T, P, Y, lanes_per_cell=0, stream=None):
     """Source term f [n][nS+1] (column 0 = dT/dt) for numpy or torch GPU inputs."""
     L = lib()
     n = int(T.shape[0])
+    _check_shapes(mech, n, P, Y)
     N = mech.n_species + 1
     if _is_torch(T):
         import torch

@@ -83,3 +83,17 @@ def test_integrate_rejects_bad_arguments_without_a_device():
     assert L.rkc_rhs(None, 4, None, None, None, None, None) == rkc.EINVAL
     assert L.rkc_mech_destroy(None) == rkc.OK
     assert L.rkc_mech_info(None, None, None, None, None) == rkc.EINVAL
+
+
+def test_binding_rejects_species_count_mismatch():
+    class FakeMech:
+        n_species = 9
+        handle = None
+    T = np.full(4, 1200.0)
+    P = np.full(4, 1e5)
+    with pytest.raises(ValueError):
+        rkc.integrate(FakeMech(), T, P, np.zeros((4, 8)), 1e-6)
+    with pytest.raises(ValueError):
+        rkc.integrate(FakeMech(), T, np.full(3, 1e5), np.zeros((4, 9)), 1e-6)
+    with pytest.raises(ValueError):
+        rkc.rhs(FakeMech(), T, P, np.zeros((4, 10)))
