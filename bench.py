@@ -123,6 +123,10 @@ def main():
                     help="replay the served mixed-request trace (13/53 species, Poisson "
                          "arrivals) through the integration server and, as the baseline, "
                          "through sequential rkc_integrate calls; report latency")
+    ap.add_argument("--study", choices=["divergence", "crossover"], default=None,
+                    help="divergence study: states sampled along ignition trajectories, "
+                         "timed in trajectory order (similar neighbours) and shuffled, with "
+                         "the plain and the persistent schedule")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-streams", type=int, default=4)
@@ -142,6 +146,12 @@ def main():
 
     if args.serve:
         serve(args)
+        return
+    if args.study == "divergence":
+        study_divergence(args)
+        return
+    if args.study == "crossover":
+        study_crossover(args)
         return
 
     cfg = args.config
@@ -276,6 +286,125 @@ def main():
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(mech, c, st, args.steps, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def trajectory_states(rkc, gm, c, synth, mech, n_traj, n_samp, seed):
+    """States sampled along constant-pressure ignition trajectories (the
+    paper's way of making initial conditions, Sec. 3): n_traj seeded starting
+    compositions at 1600 K and 1 atm, each integrated over n_samp consecutive
+    global steps of c["dt"] with rkc_integrate; sample k of trajectory j is the
+    state after k steps.  Returned in trajectory order, so neighbouring cells
+    hold similar conditions."""
+    import torch
+    st = synth.make_states(mech, n_traj, seed, T_dist=("uniform", 1600.0, 1600.0),
+                           P_dist=("const", synth.ATM), Y_dist=c["Y"])
+    dev = torch.device("cuda:0")
+    T = torch.from_numpy(st["T"]).to(dev)
+    P = torch.from_numpy(st["P"]).to(dev)
+    Y = torch.from_numpy(st["Y"]).to(dev)
+    Ts = torch.empty((n_traj, n_samp), dtype=torch.float64, device=dev)
+    Ys = torch.empty((n_traj, n_samp, mech["n_species"]), dtype=torch.float64, device=dev)
+    for k in range(n_samp):
+        Ts[:, k] = T
+        Ys[:, k] = Y
+        rkc.integrate(gm, T, P, Y, c["dt"], c["rtol"], c["atol"], status=False)
+    n = n_traj * n_samp
+    return (Ts.reshape(n).contiguous(), torch.full((n,), synth.ATM, dtype=torch.float64,
+                                                   device=dev),
+            Ys.reshape(n, mech["n_species"]).contiguous())
+
+
+def study_divergence(args):
+    """Throughput and divergence D (Sec. 3.2) for ignition-sampled states in
+    trajectory order and shuffled, plain and persistent schedules, on the
+    13-species (16 lanes per cell: 4 cells per wavefront) and the 53-species
+    (64 lanes: one cell per wavefront) sets."""
+    import torch
+
+    from paper_1309_2710_amd import rkc, synth
+
+    dev = torch.device("cuda:0")
+    rows = []
+    for cfg, n_traj in (("c2", 1024), ("c3", 512)):
+        c = synth.CONFIGS[cfg]
+        mech = synth.config_mechanism(cfg)
+        gm = rkc.Mechanism(mech)
+        T0, P, Y0 = trajectory_states(rkc, gm, c, synth, mech, n_traj, 128, 4000)
+        n = T0.shape[0]
+        perm = torch.from_numpy(np.random.default_rng(4001).permutation(n)).to(dev)
+        for order in ("trajectory", "shuffled"):
+            Ti = T0 if order == "trajectory" else T0[perm].contiguous()
+            Yi = Y0 if order == "trajectory" else Y0[perm].contiguous()
+            for sched in (rkc.SCHED_PLAIN, rkc.SCHED_PERSISTENT):
+                T, Y = Ti.clone(), Yi.clone()
+                o = rkc.integrate(gm, T, P, Y, c["dt"], c["rtol"], c["atol"], schedule=sched,
+                                  counters=True, stats=True)
+                cn = o["counters"]
+                D32 = rkc.divergence(cn, 32)
+                G = o["stats"]["lanes_per_cell"]
+                Dw = rkc.divergence(cn, 64 // G)
+                T, Y = Ti.clone(), Yi.clone()
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                for _ in range(args.steps):
+                    rkc.integrate(gm, T, P, Y, c["dt"], c["rtol"], c["atol"], schedule=sched,
+                                  status=False)
+                torch.cuda.synchronize()
+                wall = time.perf_counter() - t
+                rows.append({"set": "%dsp/%drx" % (mech["n_species"], mech["n_reactions"]),
+                             "cells": n, "order": order,
+                             "schedule": "plain" if sched == rkc.SCHED_PLAIN else "persistent",
+                             "lanes_per_cell": G, "cell_odes_per_s": n * args.steps / wall,
+                             "mean_D32": float(D32.mean().item()),
+                             "mean_D_wave": float(Dw.mean().item()),
+                             "rhs_utilisation_step1": o["stats"]["n_rhs"] / max(1, o["stats"]["n_rhs_slots"])})
+                print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    out = {"metric": "divergence study: ignition-sampled states, trajectory order vs shuffled",
+           "unit": "cell-ODEs/s", "n_gpus": 1, "steps": args.steps, "dtype": "f64",
+           "data": "synthetic", "rows": rows}
+    print(json.dumps(out), flush=True)
+
+
+def study_crossover(args):
+    """RKC against RKCK as the global step grows (Sec. 3: RKCK suits nonstiff
+    chemistry, RKC moderately stiff): the 9-species and 13-species sets, 65536
+    cells, one global step of dt from the seeded states, both methods at the
+    same tolerance; reports cell-ODEs/s per method and which is faster."""
+    import torch
+
+    from paper_1309_2710_amd import rkc, synth
+
+    dev = torch.device("cuda:0")
+    rows = []
+    for cfg in ("c1", "c2"):
+        c = synth.CONFIGS[cfg]
+        mech = synth.config_mechanism(cfg)
+        gm = rkc.Mechanism(mech)
+        st = synth.config_states(cfg)
+        n = min(65536, st["T"].shape[0])
+        T0 = torch.from_numpy(st["T"][:n]).to(dev)
+        P = torch.from_numpy(st["P"][:n]).to(dev)
+        Y0 = torch.from_numpy(st["Y"][:n]).to(dev)
+        for dt in (1e-8, 1e-7, 1e-6, 1e-5):
+            res = {}
+            for name, method in (("rkc", rkc.RKC), ("rkck", rkc.RKCK)):
+                T, Y = T0.clone(), Y0.clone()
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                o = rkc.integrate(gm, T, P, Y, dt, c["rtol"], c["atol"], method=method,
+                                  stats=True, status=False)
+                torch.cuda.synchronize()
+                wall = time.perf_counter() - t
+                res[name] = {"cell_odes_per_s": n / wall, "rhs_per_cell": o["stats"]["n_rhs"] / n,
+                             "failed": o["stats"]["n_failed"]}
+            row = {"set": "%dsp/%drx" % (mech["n_species"], mech["n_reactions"]), "dt": dt,
+                   "cells": n, "rkc": res["rkc"], "rkck": res["rkck"],
+                   "faster": max(res, key=lambda k: res[k]["cell_odes_per_s"])}
+            rows.append(row)
+            print(json.dumps(row), file=sys.stderr, flush=True)
+    out = {"metric": "RKC vs RKCK crossover in the global step", "unit": "cell-ODEs/s",
+           "n_gpus": 1, "dtype": "f64", "data": "synthetic", "rows": rows}
     print(json.dumps(out), flush=True)
 
 
@@ -442,6 +571,14 @@ def cpu_baseline(mech, c, st, steps, budget_s):
             T, Y, _ = M.integrate(T, P, Y, c["dt"], c["rtol"], c["atol"], threads=threads)
         return time.perf_counter() - t
 
+    # one host core on a small strided sample (the per-cell code is serial)
+    one = np.arange(0, n, max(1, n // 64))[:64]
+    T1, Y1 = st["T"][one].copy(), st["Y"][one].copy()
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        T1, Y1, _ = M.integrate(T1, st["P"][one], Y1, c["dt"], c["rtol"], c["atol"], threads=1)
+    one_core = len(one) * steps / (time.perf_counter() - t1)
+
     probe = np.arange(0, n, max(1, n // (4 * threads)))[:4 * threads]
     t_probe = run(probe)
     per_cell = t_probe / len(probe)
@@ -450,7 +587,7 @@ def cpu_baseline(mech, c, st, steps, budget_s):
     idx = np.arange(0, n, max(1, n // m))[:m]
     t = run(idx)
     return {"value": len(idx) * steps / t, "unit": "cell-ODEs/s", "cores": threads,
-            "kind": "oracle",
+            "kind": "oracle", "one_core_value": one_core,
             "sample": "%d of %d cells (stride %d), %d consecutive global steps, %.1f s"
                       % (len(idx), n, max(1, n // m), steps, t)}
 

@@ -262,6 +262,22 @@ __device__ __forceinline__ double log_pos(double x) {
     return (x > 0.0 && x <= 0x1.fffffffffffffp+1023) ? r : __builtin_nan("");
 }
 
+// x^(-1/3) for a positive finite x.  With x = m 2^e and e = 3q + t,
+// t in {0, 1, 2}: x^(-1/3) = a^(-1/3) 2^(-q), a = m 2^t in [1/2, 4).  A
+// single-precision seed of a^(-1/3) (hardware log2 and exp2) is refined by two
+// Newton steps for y^-3 = a, y <- y (4 - a y^3)/3, each squaring the relative
+// error (1e-7 -> 1e-13 -> below rounding).  Within a few ulps.
+__device__ __forceinline__ double rcbrt_pos(double x) {
+    int e;
+    const double m = frexp(x, &e);
+    const int q = (e >= 0) ? e / 3 : -((2 - e) / 3);
+    const double a = __builtin_ldexp(m, e - 3 * q);
+    double y = (double)__builtin_amdgcn_exp2f(__builtin_amdgcn_logf((float)a) * (-1.0f / 3.0f));
+    y = y * __builtin_fma(-a, y * y * y, 4.0) * (1.0 / 3.0);
+    y = y * __builtin_fma(-a, y * y * y, 4.0) * (1.0 / 3.0);
+    return __builtin_ldexp(y, -q);
+}
+
 // 1/x for a positive normal x: hardware reciprocal refined by two Newton
 // steps (each doubles the correct bits; the result is within an ulp).
 __device__ __forceinline__ double rcp_nr(double x) {
@@ -279,6 +295,31 @@ __device__ __forceinline__ uint32_t opaque_zero() {
     uint32_t z;
     asm volatile("v_mov_b32 %0, 0" : "=v"(z));
     return z;
+}
+
+// One lane's gather segments of SL terms each (SL even): all of a segment's
+// words and rates are loaded before they are summed (in term order, the same
+// sum as a running accumulator), so the loads overlap instead of each waiting
+// for the previous add.
+template <int G, int SL>
+__device__ __forceinline__ void gather_segments(const uint32_t *tw, const unsigned char *Qb,
+                                                double *__restrict__ piece, int NSEG, int go) {
+    constexpr int H = SL / 2;
+    for (int sg = 0; sg < NSEG; ++sg) {
+        uint32_t w[H];
+#pragma unroll
+        for (int e = 0; e < H; ++e) w[e] = tw[(sg * H + e) * G];
+        double v[SL];
+#pragma unroll
+        for (int e = 0; e < H; ++e) {
+            v[2 * e] = *reinterpret_cast<const double *>(Qb + (w[e] & 0xffffu));
+            v[2 * e + 1] = *reinterpret_cast<const double *>(Qb + (w[e] >> 16));
+        }
+        double acc = v[0];
+#pragma unroll
+        for (int e = 1; e < SL; ++e) acc += v[e];
+        piece[sg * G + go] = acc;
+    }
 }
 
 // Source term of E:mass and E:energy for the group's cell at state z.
@@ -347,22 +388,31 @@ __device__ __forceinline__ void rhs_eval(const double (&z)[NSL], double P10, dou
 #pragma unroll
         for (int r = 0; r < RUC; ++r) Q[r * G + go] = q[r];
     } else {
+        // LDS copy is lane-interleaved: 16-byte piece q of unit r * G + g at
+        // double2 index (4 r + q) G + g, so a wave's reads are contiguous.  The
+        // reactant slots (piece 3) of the next unit are loaded one iteration
+        // ahead; the load after the last unit reads the group arrays that
+        // follow the table in LDS and is not used.
+        const double2 *ub = reinterpret_cast<const double2 *>(L.units) + g;
+        double2 u3n = ub[3 * G];
         for (int r = 0; r < RU; ++r) {
             const int p = r * G + g;
-            // LDS copy is lane-interleaved: 16-byte piece q of unit r * G + g at
-            // double2 index (4 r + q) G + g, so a wave's reads are contiguous
-            const double2 *u = reinterpret_cast<const double2 *>(L.units) + (size_t)(4 * r) * G + g;
-            const double2 u0 = u[0], u1 = u[G], u2 = u[2 * G], u3 = u[3 * G];
+            const double2 *u = ub + (size_t)(4 * r) * G;
+            // reactant slots first: the concentration products load and
+            // multiply while the two exponentials are computed
+            const double2 u3 = u3n;
+            const double2 u0 = u[0], u1 = u[G], u2 = u[2 * G];
+            u3n = u[7 * G];
             const uint64_t a = __double_as_longlong(u3.x), b = __double_as_longlong(u3.y);
-            const double kf = exp_cw(u0.x + u0.y * lnT - u1.x * invT);
-            const double kr = exp_cw(u1.y + u2.x * lnT - u2.y * invT);
             const unsigned char *Cb = reinterpret_cast<const unsigned char *>(C);
             auto cat = [&](uint64_t o, int sl) {
                 return *reinterpret_cast<const double *>(Cb + ((o >> (16 * sl)) & 0xffffu));
             };
-            const double of = kf * cat(a, 0) * cat(a, 1) * cat(a, 2);
-            const double orv = kr * cat(b, 0) * cat(b, 1) * cat(b, 2);
-            Q[p] = of - orv;
+            const double cf = cat(a, 0) * cat(a, 1) * cat(a, 2);
+            const double cr = cat(b, 0) * cat(b, 1) * cat(b, 2);
+            const double kf = exp_cw(u0.x + u0.y * lnT - u1.x * invT);
+            const double kr = exp_cw(u1.y + u2.x * lnT - u2.y * invT);
+            Q[p] = kf * cf - kr * cr;
         }
     }
     wave_sync();
@@ -372,16 +422,24 @@ __device__ __forceinline__ void rhs_eval(const double (&z)[NSL], double P10, dou
     {
         const unsigned char *Qb = reinterpret_cast<const unsigned char *>(Q);
         const uint32_t *tw = L.gather + go;
-        const int half = SEGL >> 1;
-        for (int sg = 0; sg < NSEG; ++sg) {
-            double acc = 0.0;
+        switch (SEGL) {   // uniform; the common segment lengths are unrolled
+        case 2: gather_segments<G, 2>(tw, Qb, piece, NSEG, go); break;
+        case 4: gather_segments<G, 4>(tw, Qb, piece, NSEG, go); break;
+        case 6: gather_segments<G, 6>(tw, Qb, piece, NSEG, go); break;
+        case 8: gather_segments<G, 8>(tw, Qb, piece, NSEG, go); break;
+        default: {
+            const int half = SEGL >> 1;
+            for (int sg = 0; sg < NSEG; ++sg) {
+                double acc = 0.0;
 #pragma unroll 4
-            for (int e2 = 0; e2 < half; ++e2) {
-                const uint32_t w = tw[(sg * half + e2) * G];
-                acc += *reinterpret_cast<const double *>(Qb + (w & 0xffffu));
-                acc += *reinterpret_cast<const double *>(Qb + (w >> 16));
+                for (int e2 = 0; e2 < half; ++e2) {
+                    const uint32_t w = tw[(sg * half + e2) * G];
+                    acc += *reinterpret_cast<const double *>(Qb + (w & 0xffffu));
+                    acc += *reinterpret_cast<const double *>(Qb + (w >> 16));
+                }
+                piece[sg * G + go] = acc;
             }
-            piece[sg * G + go] = acc;
+        }
         }
     }
     wave_sync();

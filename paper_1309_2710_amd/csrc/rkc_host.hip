@@ -146,6 +146,43 @@ struct GatherPlan {
     std::vector<int32_t> ps;       // [2 NK + 1]
 };
 
+// Order the terms inside each chunk so that at every position the lanes of a
+// 16-lane LDS pass read distinct banks where they can: a double at byte offset
+// o uses the bank pair (o / 8) mod 32, and lanes reading the same address are
+// served together.  Greedy per pass: each lane takes, among its remaining
+// terms, one whose bank pair is free or already holds that very address, else
+// the least loaded one.  Only the order of a chunk's sum changes (rounding).
+void order_for_banks(std::vector<uint32_t> *cellp, int NSEG, int G, int L) {
+    std::vector<uint32_t> &cell = *cellp;
+    const int PASS = std::min(16, G);
+    for (int sg = 0; sg < NSEG; ++sg) {
+        std::vector<std::vector<uint32_t>> left(G);
+        for (int g = 0; g < G; ++g)
+            left[g].assign(cell.begin() + ((size_t)sg * G + g) * L,
+                           cell.begin() + ((size_t)sg * G + g + 1) * L);
+        for (int e = 0; e < L; ++e) {
+            for (int p0 = 0; p0 < G; p0 += PASS) {
+                std::vector<std::vector<uint32_t>> bank(32);
+                for (int g = p0; g < p0 + PASS; ++g) {
+                    size_t best = 0, best_cost = (size_t)-1;
+                    for (size_t k = 0; k < left[g].size(); ++k) {
+                        const uint32_t a = left[g][k];
+                        const std::vector<uint32_t> &u = bank[(a / 8) % 32];
+                        const bool same = std::find(u.begin(), u.end(), a) != u.end();
+                        const size_t cost = (u.empty() || same) ? 0 : u.size();
+                        if (cost < best_cost) { best_cost = cost; best = k; }
+                    }
+                    const uint32_t a = left[g][best];
+                    left[g].erase(left[g].begin() + (long)best);
+                    std::vector<uint32_t> &u = bank[(a / 8) % 32];
+                    if (std::find(u.begin(), u.end(), a) == u.end()) u.push_back(a);
+                    cell[((size_t)sg * G + g) * L + e] = a;
+                }
+            }
+        }
+    }
+}
+
 int plan_gather(const rkc_mech *m, int G, int NK, int RU, GatherPlan *gp) {
     const int RUG = RU * G;
     if ((size_t)(RUG + 1) * 8 > rkcdev::TERM_MAX_BYTES) return RKC_ENOTSUP;
@@ -171,8 +208,9 @@ int plan_gather(const rkc_mech *m, int G, int NK, int RU, GatherPlan *gp) {
     }
     const int L = gp->SEGL;
     const int half = L / 2;
-    gp->words.assign((size_t)gp->NSEG * half * G, zero_term | (zero_term << 16));
     gp->ps.assign(2 * (size_t)NK + 1, 0);
+    // terms of chunk (segment sg, lane g) at cell[(sg G + g) L + e], zero-padded
+    std::vector<uint32_t> cell((size_t)gp->NSEG * G * L, zero_term);
     int c = 0;
     for (int k = 0; k < NK; ++k) {
         for (int sign = 0; sign < 2; ++sign) {
@@ -181,14 +219,20 @@ int plan_gather(const rkc_mech *m, int G, int NK, int RU, GatherPlan *gp) {
             const std::vector<uint32_t> &t = lists[2 * (k - 1) + sign];
             for (size_t b = 0; b < t.size(); b += L, ++c) {
                 const int g = c % G, sg = c / G;
-                for (int e = 0; e < L; ++e) {
-                    const uint32_t term = (b + e < t.size()) ? t[b + e] : zero_term;
-                    uint32_t &w = gp->words[(size_t)(sg * half + e / 2) * G + g];
-                    w = (e % 2) ? ((w & 0xffffu) | (term << 16)) : ((w & 0xffff0000u) | term);
-                }
+                for (int e = 0; e < L && b + e < t.size(); ++e)
+                    cell[((size_t)sg * G + g) * L + e] = t[b + e];
             }
         }
     }
+    order_for_banks(&cell, gp->NSEG, G, L);
+    gp->words.assign((size_t)gp->NSEG * half * G, 0u);
+    for (int sg = 0; sg < gp->NSEG; ++sg)
+        for (int g = 0; g < G; ++g)
+            for (int e = 0; e < L; ++e) {
+                const uint32_t term = cell[((size_t)sg * G + g) * L + e];
+                uint32_t &w = gp->words[(size_t)(sg * half + e / 2) * G + g];
+                w = (e % 2) ? ((w & 0xffffu) | (term << 16)) : ((w & 0xffff0000u) | term);
+            }
     gp->ps[2 * NK] = c;
     if (c > gp->NSEG * G) return RKC_ENOTSUP;   // cannot happen by construction
     return RKC_OK;

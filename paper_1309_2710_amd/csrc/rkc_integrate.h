@@ -176,7 +176,7 @@ __device__ __forceinline__ double rms_norm(const double (&d)[NSL], const double 
 // between source-term evaluations, so it does not occupy registers while the
 // evaluation runs.  Every lane of the group writes identical values.
 struct RkcState {
-    double t, h, sigma, sigma_prev, delta, ht, h_prev, lerr_prev, P10, invP10;
+    double t, h, sigma, sigma_prev, delta, ht, h_prev, rprev, P10, invP10;
     double w0, w1, Tm1, Tm2, Tpm1, Tpm2, Tppm1, Tppm2, bm1, ibm1, ibm2;
     int cell, phase, k_pow, s, j, last, need_sigma, since_sigma, predictive, after, tab;
     Counts c;
@@ -217,7 +217,7 @@ __global__ __launch_bounds__((Occ<RUC, NSL>::threads), (Occ<RUC, NSL>::waves)) v
                 S.invP10 = 1.0 / P10;
                 S.c = Counts{0, 0, 0, 0, 0, 0, 0};
                 S.t = 0.0; S.need_sigma = 0; S.since_sigma = 0; S.predictive = 0;
-                S.h_prev = 0.0; S.lerr_prev = 0.0;
+                S.h_prev = 0.0; S.rprev = 0.0;
 #pragma unroll
                 for (int i = 0; i < NSL; ++i) z[i] = y[i];
                 S.phase = PH_F0;
@@ -308,23 +308,29 @@ __global__ __launch_bounds__((Occ<RUC, NSL>::threads), (Occ<RUC, NSL>::waves)) v
                         const int ss = S.since_sigma + 1;
                         S.since_sigma = ss;
                         S.need_sigma = (ss >= 25);
-                        // err^a as exp(a log err): one logarithm per step
-                        const double lerr = log_pos(err);
-                        double fac;
-                        if (err == 0.0) fac = 10.0;
-                        else if (!S.predictive) fac = 0.8 * exp_cw(-lerr / 3.0);
-                        else fac = 0.8 * (h / S.h_prev) * exp_cw((S.lerr_prev - 2.0 * lerr) / 3.0);
+                        // with r = err^(-1/3) and r_prev = err_prev^(-1/3) the
+                        // predictive factor is 0.8 (h/h_prev) r^2 / r_prev; an
+                        // err_prev of 0 is kept as r_prev = 0 (factor 0)
+                        double fac, r = 0.0;
+                        if (err == 0.0) {
+                            fac = 10.0;
+                        } else {
+                            r = rcbrt_pos(err);
+                            if (!S.predictive) fac = 0.8 * r;
+                            else if (S.rprev == 0.0) fac = 0.0;
+                            else fac = 0.8 * h * r * r * rcp_nr(S.h_prev * S.rprev);
+                        }
                         if (fac > 10.0) fac = 10.0;
                         if (fac < 0.1) fac = 0.1;
                         S.h_prev = h;
-                        S.lerr_prev = lerr;
+                        S.rprev = r;
                         S.predictive = 1;
                         S.h = h * fac;
                         act = ACT_BEGIN_STEP;
                     }
                 } else {
                     c.n_reject += 1;
-                    double fac = isfinite(err) ? 0.8 * exp_cw(-log_pos(err) / 3.0) : 0.1;
+                    double fac = isfinite(err) ? 0.8 * rcbrt_pos(err) : 0.1;
                     if (fac < 0.1) fac = 0.1;
                     S.h = h * fac;
                     S.need_sigma = 1;

@@ -181,3 +181,28 @@ def test_full_size_c3_sampled(R):
                               c["atol"], threads=THREADS)
     rep = PT.check(Tg[idx], Yg[idx], cg[idx], To, Yo, co, c["rtol"], c["atol"], max_flips("c3", 64))
     _say(rep)
+
+
+def test_ten_consecutive_steps_c3(R):
+    """The paper's protocol times ten consecutive global steps (Sec. 3): parity
+    after step 1 and after step 10 on a strided sample of the 53-species set,
+    each step restarting from the previous result on both sides."""
+    _say("ten steps c3")
+    gm, om = mech(R, "c3")
+    c = synth.CONFIGS["c3"]
+    st = synth.config_states("c3")
+    idx = np.arange(0, st["T"].shape[0], 4096)[:32]
+    Tg, Yg = st["T"][idx].copy(), st["Y"][idx].copy()
+    To, Yo = Tg.copy(), Yg.copy()
+    P = st["P"][idx].copy()
+    same = np.ones(len(idx), bool)
+    for k in range(10):
+        out = R.integrate(gm, Tg, P, Yg, c["dt"], c["rtol"], c["atol"], counters=True)
+        To, Yo, co = om.integrate(To, P, Yo, c["dt"], c["rtol"], c["atol"], threads=THREADS)
+        same &= ~PT.counter_mismatch(out["counters"], co)
+        if k in (0, 9):
+            err = PT.rel_err(Tg, Yg, To, Yo)
+            _say("step", k + 1, "max err (same decisions so far)",
+                 err[same].max() if same.any() else None, "cells", int(same.sum()))
+            assert same.sum() >= len(idx) - max_flips("c3", len(idx))
+            assert err[same].max() <= PT.TOL
