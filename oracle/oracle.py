@@ -24,7 +24,9 @@ class _Mech(ct.Structure):
     _fields_ = [("n_species", ct.c_int), ("n_reactions", ct.c_int),
                 ("W", ct.c_void_p), ("nasa_low", ct.c_void_p), ("nasa_high", ct.c_void_p),
                 ("T_mid", ct.c_void_p), ("reac", ct.c_void_p), ("prod", ct.c_void_p),
-                ("A", ct.c_void_p), ("beta", ct.c_void_p), ("Ea", ct.c_void_p)]
+                ("A", ct.c_void_p), ("beta", ct.c_void_p), ("Ea", ct.c_void_p),
+                ("pdep", ct.c_void_p), ("eff", ct.c_void_p), ("A0", ct.c_void_p),
+                ("beta0", ct.c_void_p), ("Ea0", ct.c_void_p), ("troe", ct.c_void_p)]
 
 
 class Counters(ct.Structure):
@@ -83,10 +85,20 @@ class Model:
             "beta": np.ascontiguousarray(mech["beta"], dtype=np.float64),
             "Ea": np.ascontiguousarray(mech["Ea"], dtype=np.float64),
         }
+        opt = {}
+        if mech.get("pdep") is not None:
+            opt = {"pdep": np.ascontiguousarray(mech["pdep"], dtype=np.int32),
+                   "eff": np.ascontiguousarray(mech["eff"], dtype=np.float64),
+                   "A0": np.ascontiguousarray(mech["A0"], dtype=np.float64),
+                   "beta0": np.ascontiguousarray(mech["beta0"], dtype=np.float64),
+                   "Ea0": np.ascontiguousarray(mech["Ea0"], dtype=np.float64),
+                   "troe": np.ascontiguousarray(mech["troe"], dtype=np.float64)}
+        self._keep.update(opt)
         k = self._keep
+        pd = [_p(k[x]) if x in k else None for x in ("pdep", "eff", "A0", "beta0", "Ea0", "troe")]
         self._m = _Mech(self.n_species, self.n_reactions, _p(k["W"]), _p(k["nasa_low"]),
                         _p(k["nasa_high"]), _p(k["T_mid"]), _p(k["reac"]), _p(k["prod"]),
-                        _p(k["A"]), _p(k["beta"]), _p(k["Ea"]))
+                        _p(k["A"]), _p(k["beta"]), _p(k["Ea"]), *pd)
         self._h = L.orc_model_create(ct.byref(self._m))
 
     def __del__(self):

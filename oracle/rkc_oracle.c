@@ -57,6 +57,18 @@ typedef struct {
     const int32_t *reac;      /* [nR][3] species index with repetition, -1 empty */
     const int32_t *prod;      /* [nR][3] */
     const double *A, *beta, *Ea;  /* [nR] */
+    /* Pressure dependence (Sec. 2.2 after E:rxn-rate: third-body and falloff
+     * reactions in the Chemkin formulation the paper refers to).  Any pointer
+     * may be NULL: no reaction of that kind.
+     *   pdep [nR]      0 plain, 1 third body, 2 Lindemann falloff, 3 Troe falloff
+     *   eff  [nR][nS]  third-body efficiencies alpha (NULL: all 1)
+     *   A0, beta0, Ea0 [nR]  low-pressure limit k_0 of falloff reactions
+     *   troe [nR][4]   a, T3, T1, T2 (the Troe temperatures; T2 <= 0: its term
+     *                  absent) */
+    const int32_t *pdep;
+    const double *eff;
+    const double *A0, *beta0, *Ea0;
+    const double *troe;
 } orc_mech;
 
 /* Per-species list of (reaction, nu'' - nu') with nonzero coefficient, in
@@ -111,6 +123,23 @@ void orc_model_destroy(orc_model *md) {
 /* Scratch for one RHS evaluation. */
 typedef struct { double *C, *omega, *Omega; } rhs_ws;
 
+/* Troe broadening factor F(T, Pr) (Chemkin form), with the three Troe
+ * temperatures written T3 (T-triple-star), T1 (T-star) and T2 (T-double-star):
+ *   F_cent = (1 - a) exp(-T / T3) + a exp(-T / T1) + exp(-T2 / T)
+ *   c = -0.4 - 0.67 log10 F_cent, n = 0.75 - 1.27 log10 F_cent, d = 0.14
+ *   log10 F = log10 F_cent / (1 + ((log10 Pr + c) / (n - d (log10 Pr + c)))^2) */
+static double troe_F(double T, double Pr, const double *t) {
+    const double a = t[0], T3 = t[1], T1 = t[2], T2 = t[3];
+    double Fc = (1.0 - a) * exp(-T / T3) + a * exp(-T / T1);
+    if (T2 > 0.0) Fc += exp(-T2 / T);
+    const double lFc = log10(Fc);
+    const double c = -0.4 - 0.67 * lFc;
+    const double n = 0.75 - 1.27 * lFc;
+    const double x = log10(Pr) + c;
+    const double f1 = x / (n - 0.14 * x);
+    return pow(10.0, lFc / (1.0 + f1 * f1));
+}
+
 /* f(y) for the constant-pressure adiabatic kinetics system, Sec. 2.2. */
 static void rhs_eval(const orc_model *md, double P, const double *y, double *f, rhs_ws *ws) {
     const orc_mech *m = &md->m;
@@ -128,6 +157,25 @@ static void rhs_eval(const orc_model *md, double P, const double *y, double *f, 
     /* (E:rxn-const) and (E:rxn-rate) */
     for (int j = 0; j < nR; ++j) {
         double k = m->A[j] * pow(T, m->beta[j]) * exp(-m->Ea[j] / (R_J * T));
+        const int kind = m->pdep ? m->pdep[j] : 0;
+        if (kind != 0) {
+            /* third-body concentration [M] = sum_i alpha_ji C_i */
+            double M = 0.0;
+            for (int i = 0; i < nS; ++i) M += (m->eff ? m->eff[(size_t)j * nS + i] : 1.0) * ws->C[i];
+            if (kind == 1) {
+                k = k * M;
+            } else {
+                /* falloff: k = k_inf Pr / (1 + Pr) F, Pr = k_0 [M] / k_inf */
+                const double k0 = m->A0[j] * pow(T, m->beta0[j]) * exp(-m->Ea0[j] / (R_J * T));
+                if (k == 0.0 || k0 * M == 0.0) {
+                    k = 0.0;
+                } else {
+                    const double Pr = k0 * M / k;
+                    const double F = (kind == 3) ? troe_F(T, Pr, m->troe + 4 * (size_t)j) : 1.0;
+                    k = k * (Pr / (1.0 + Pr)) * F;
+                }
+            }
+        }
         double Om = k;
         for (int s = 0; s < 3; ++s) {
             int sp = m->reac[3 * j + s];

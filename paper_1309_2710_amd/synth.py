@@ -408,6 +408,14 @@ CONFIGS = {
                T=("uniform", 800.0, 2200.0), P=("const", ATM), Y=("majors", 5, 0.90, 0.99),
                dt=1e-6, rtol=1e-6, atol=1e-10, ea_max=2e5, T_range=(750.0, 2300.0),
                P_max=ATM, s_target=30, label="53sp/634rx, 131072 cells, dt 1e-6"),
+    # the 53-species set with pressure-dependent pairs (third body and falloff,
+    # about 9 % each of the reaction pairs, as in GRI-Mech-sized mechanisms)
+    "c3p": dict(n_species=53, n_reactions=634, elements=["H", "O", "C", "N", "Ar"],
+                mech_seed=1003, pdep_seed=1103, pdep_frac=(0.09, 0.09), state_seed=2003,
+                n_cells=131072, T=("uniform", 800.0, 2200.0), P=("const", ATM),
+                Y=("majors", 5, 0.90, 0.99), dt=1e-6, rtol=1e-6, atol=1e-10, ea_max=2e5,
+                T_range=(750.0, 2300.0), P_max=ATM, s_target=30,
+                label="53sp/634rx with third-body and falloff pairs, 131072 cells, dt 1e-6"),
     "c4": dict(n_species=111, n_reactions=1566, elements=["H", "O", "C", "N", "Ar"],
                mech_seed=1004, state_seed=2004, n_cells=65536,
                T=("bimodal", 800.0, 2400.0, 20.0), P=("const", ATM), Y=("dirichlet",),
@@ -428,10 +436,79 @@ def _cached_mech(name):
                        ea_max=c["ea_max"], T_lo=c["T_range"][0], T_hi=c["T_range"][1],
                        P_max=c["P_max"], dt=c["dt"], s_target=c["s_target"],
                        name=name, **kw)
+    if "pdep_seed" in c:
+        m = add_pressure_dependence(m, c["pdep_seed"], c["pdep_frac"][0], c["pdep_frac"][1],
+                                    T_ref=math.sqrt(c["T_range"][0] * c["T_range"][1]),
+                                    P_ref=c["P_max"])
     if c["Y"][0] == "majors":
         rng = np.random.Generator(np.random.PCG64(c["mech_seed"] + 7))
         m["major_species"] = sorted(rng.choice(c["n_species"] - 1, size=c["Y"][1],
                                                replace=False).tolist())
+    return m
+
+
+PDEP_PLAIN, PDEP_THIRD_BODY, PDEP_LINDEMANN, PDEP_TROE = 0, 1, 2, 3
+
+
+def add_pressure_dependence(mech, seed, frac_tb, frac_fo, *, T_ref, P_ref, n_sets=3):
+    """A copy of a pair-structured mechanism in which a seeded fraction of the
+    forward/reverse pairs become third-body pairs (rate k [M] prod C) and
+    falloff pairs (Lindemann or Troe), the pressure-dependent forms the paper
+    also evaluates (Sec. 2.2, after E:rxn-rate; Chemkin conventions).
+
+    Added keys: pdep [nR] (0 plain, 1 third body, 2 Lindemann, 3 Troe),
+    eff [nR][nS] third-body efficiencies (n_sets distinct vectors: six species
+    with efficiency in {0.7, 1.5, 2, 3, 6, 12}, the rest 1), A0/beta0/Ea0 [nR]
+    low-pressure limits, troe [nR][4] (a, T***, T*, T**; T** = 0: term absent).
+    Both reactions of a pair get the same kind, efficiencies and Troe
+    parameters.  Third body: A is divided by C_ref * e_max (C_ref the total
+    concentration at T_ref, P_ref; e_max the largest efficiency) so the
+    effective rate stays under the original stiffness bound.  Falloff: k_inf is
+    the pair's original rate; k_0 = k_inf * 10^U(-1, 1) / C_ref for each
+    direction (the same factor, so the reverse k_0 / k_inf ratio matches the
+    forward one and the Appendix A fit of the reverse carries over); the
+    falloff rate never exceeds k_inf."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    m = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in mech.items()}
+    nS, nR = m["n_species"], m["n_reactions"]
+    n_pairs = nR // 2
+    c_ref = P_ref * 10.0 / (R_ERG * T_ref)
+    sets = np.ones((n_sets, nS))
+    for q in range(n_sets):
+        sp = rng.choice(nS, size=min(6, nS), replace=False)
+        sets[q, sp] = rng.choice([0.7, 1.5, 2.0, 3.0, 6.0, 12.0], size=len(sp))
+    pdep = np.zeros(nR, np.int32)
+    eff = np.ones((nR, nS))
+    A0 = np.zeros(nR)
+    beta0 = np.zeros(nR)
+    Ea0 = np.zeros(nR)
+    troe = np.zeros((nR, 4))
+    order = rng.permutation(n_pairs)
+    n_tb = int(round(frac_tb * n_pairs))
+    n_fo = int(round(frac_fo * n_pairs))
+    for k, pr in enumerate(order[:n_tb + n_fo]):
+        j = 2 * int(pr)
+        q = int(rng.integers(n_sets))
+        if k < n_tb:
+            kind = PDEP_THIRD_BODY
+            for jj in (j, j + 1):
+                m["A"][jj] = m["A"][jj] / (c_ref * sets[q].max())
+        else:
+            kind = PDEP_TROE if rng.random() < 2.0 / 3.0 else PDEP_LINDEMANN
+            fac = 10.0 ** rng.uniform(-1.0, 1.0) / c_ref
+            for jj in (j, j + 1):
+                A0[jj] = m["A"][jj] * fac
+                beta0[jj] = m["beta"][jj]
+                Ea0[jj] = m["Ea"][jj]
+            if kind == PDEP_TROE:
+                t = (rng.uniform(0.1, 0.9), 10.0 ** rng.uniform(1.0, 3.0),
+                     10.0 ** rng.uniform(3.0, 4.0),
+                     rng.uniform(1000.0, 8000.0) if rng.random() < 0.5 else 0.0)
+                troe[j] = troe[j + 1] = t
+        pdep[j] = pdep[j + 1] = kind
+        eff[j] = eff[j + 1] = sets[q]
+    m.update(pdep=pdep, eff=eff, A0=A0, beta0=beta0, Ea0=Ea0, troe=troe,
+             name=mech.get("name", "mech") + "_pdep")
     return m
 
 

@@ -95,7 +95,7 @@ def _cp_mass(m, T, Y):
     return out
 
 
-@pytest.mark.parametrize("cfg", ["c1", "c2", "c3", "c4"])
+@pytest.mark.parametrize("cfg", ["c1", "c2", "c3", "c4", "c3p"])
 def test_conservation_invariants(cfg):
     """Mass: sum_i dY_i/dt = 0.  Elements: sum_i n_ei/W_i dY_i/dt = 0.
     Adiabatic constant pressure: sum_i h_i dY_i/dt + cp dT/dt = 0 (exact identity
