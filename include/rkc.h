@@ -105,7 +105,29 @@ typedef struct {
     const int32_t *reac;
     const int32_t *prod;
     const double *A, *beta, *Ea;
+    /* Optional pressure dependence (the third-body and falloff reactions of
+     * Sec. 2.2, Chemkin formulation); pdep = NULL means every reaction plain.
+     *   pdep   [n_reactions]              RKC_PDEP_* kind of each reaction
+     *   eff    [n_reactions][n_species]   third-body efficiencies alpha, used by
+     *                                     kinds 1-3 ([M] = sum alpha_i C_i); NULL = 1
+     *   A0, beta0, Ea0 [n_reactions]      low-pressure limit k_0 of falloff
+     *                                     reactions (units of A times cm^3/mol)
+     *   troe   [n_reactions][4]           Troe a, T3, T1, T2 (K; T2 <= 0: the
+     *                                     exp(-T2/T) term is absent)
+     * Third body: rate k [M] prod C.  Falloff: k = k_inf Pr/(1 + Pr) F with
+     * Pr = k_0 [M] / k_inf, F = 1 (Lindemann) or the Troe form; k = 0 when
+     * k_inf or k_0 [M] is 0. */
+    const int32_t *pdep;
+    const double *eff;
+    const double *A0, *beta0, *Ea0;
+    const double *troe;
 } rkc_mech_desc;
+
+/* Kinds of rkc_mech_desc.pdep. */
+#define RKC_PDEP_PLAIN      0
+#define RKC_PDEP_THIRD_BODY 1
+#define RKC_PDEP_LINDEMANN  2
+#define RKC_PDEP_TROE       3
 
 /* Options; rkc_opts_default() fills the defaults shown. */
 typedef struct {
@@ -146,7 +168,9 @@ int rkc_opts_default(rkc_opts *opts);
 /* Validate a mechanism, pack its tables and upload them to the current HIP
  * device.  On success *out owns device memory until rkc_mech_destroy.
  * Errors: RKC_EINVAL (sizes < 1, index out of range, > 3 molecules per side,
- * W <= 0, non-finite parameter, A < 0), RKC_ENOTSUP (n_species > 1021),
+ * W <= 0, non-finite parameter, A < 0, a pdep kind outside 0..3, a falloff
+ * reaction without A0/beta0/Ea0, a Troe reaction without troe or with
+ * T3 <= 0 or T1 <= 0, a negative efficiency), RKC_ENOTSUP (n_species > 1021),
  * RKC_ENOMEM, RKC_EDEVICE. */
 int rkc_mech_create(const rkc_mech_desc *desc, rkc_mech **out);
 

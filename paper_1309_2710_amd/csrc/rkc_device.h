@@ -59,8 +59,21 @@ enum {
 //   [7]    bit pattern: the reverse reaction's reactant slots, same layout
 constexpr int UNIT_DOUBLES = 8;
 
+// Pressure-dependent unit record (third body and falloff), 12 doubles:
+//   [0] bit pattern: kind (bits 0..7; 1 third body, 2 Lindemann, 3 Troe) and
+//       efficiency set (bits 8..15)
+//   [1..3] ln A0, beta0, theta0 of the forward low-pressure limit k_0
+//   [4..6] the same for the reverse reaction (ln A0 = -1e4 if unpaired)
+//   [7] unused; [8..11] Troe a, 1/T3, 1/T1, T2 (T2 <= 0: term absent)
+// Units of the rounds that hold pressure-dependent units have one record each
+// (kind 0 for the plain ones there), lane-interleaved like the unit records.
+constexpr int PDEP_DOUBLES = 12;
+constexpr int MAX_EFFSETS = 16;
+
 struct Tables {
     const double *units;     // [RU * G][8]
+    const double *pdep;      // [NPR * G][12], interleaved by lane (rounds RUp..RU-1)
+    const double *eff;       // [NMS][NK] third-body efficiencies by state index
     const double *spec;      // [NFIELD][NK]
     const uint32_t *gather;  // [NSEG * SEGL / 2][G]: two 16-bit terms per word
     const int32_t *ps;       // [2 NK + 1]: pieces of state index k are
@@ -73,6 +86,8 @@ constexpr uint32_t TERM_MAX_BYTES = 0xffffu;
 
 struct Params {
     int nS, N, NK, nU, RU, NSEG, SEGL;
+    int RUp, NPR, NMS;               // first round with pressure-dependent units, their
+                                     // rounds (RUp + NPR = RU), efficiency sets
     Tables tab;
     int n_cells;
     double *T;
@@ -207,6 +222,9 @@ struct GroupLds {
     const uint32_t *gather;
     const int32_t *ps;
     const double *units;   // LDS copy (RUC == 0 only)
+    const double *pdep;    // pressure-dependent records of rounds RUp.. (LDS)
+    const double *eff;     // [NMS][NK] efficiency sets (LDS)
+    double *Mv;            // [NMS] third-body concentrations of the sets
     double *C;             // [NK] concentrations, C[nS] == 1.0
     double *Q;             // [RU G + 2]: net rates q, then a zero slot
     double *piece;         // [NSEG * G] partial sums of the gather
@@ -297,6 +315,25 @@ __device__ __forceinline__ uint32_t opaque_zero() {
     return z;
 }
 
+constexpr double INV_LN10 = 0.43429448190325182765;   // 1 / ln 10
+constexpr double LN10 = 2.30258509299404568402;
+
+// Falloff rate k_inf Pr/(1 + Pr) F with Pr = k_0 [M] / k_inf (Chemkin form);
+// F = 1 (Lindemann) or the Troe factor with log10 F = lFc / (1 + f^2),
+// f = (log10 Pr + c) / (n - 0.14 (log10 Pr + c)), c = -0.4 - 0.67 lFc,
+// n = 0.75 - 1.27 lFc, lFc = log10 F_cent.  Zero if k_inf or k_0 [M] is 0.
+__device__ __forceinline__ double falloff_rate(double kinf, double k0M, double lFc, bool troe) {
+    if (!(kinf > 0.0) || !(k0M > 0.0)) return 0.0;
+    const double Pr = k0M / kinf;
+    double F = 1.0;
+    if (troe) {
+        const double x = log_pos(Pr) * INV_LN10 + (-0.4 - 0.67 * lFc);
+        const double f = x / ((0.75 - 1.27 * lFc) - 0.14 * x);
+        F = exp_cw(lFc / (1.0 + f * f) * LN10);
+    }
+    return kinf * (Pr / (1.0 + Pr)) * F;
+}
+
 // One lane's gather segments of SL terms each (SL even): all of a segment's
 // words and rates are loaded before they are summed (in term order, the same
 // sum as a running accumulator), so the loads overlap instead of each waiting
@@ -324,11 +361,11 @@ __device__ __forceinline__ void gather_segments(const uint32_t *tw, const unsign
 
 // Source term of E:mass and E:energy for the group's cell at state z.
 // z/fz hold this lane's NSL elements (index k = s * G + g).
-template <int G, int NSL, int RUC>
+template <int G, int NSL, int RUC, bool PD>
 __device__ __forceinline__ void rhs_eval(const double (&z)[NSL], double P10, double invP10,
                                          double (&fz)[NSL], const GroupLds &L,
                                          const UnitRegs<RUC> &ur, int g, int N, int RU, int NSEG,
-                                         int SEGL) {
+                                         int SEGL, int RUp, int NMS) {
     constexpr int NK = NSL * G;
     const uint32_t oz = opaque_zero();
     const int go = g + (int)oz;
@@ -365,10 +402,21 @@ __device__ __forceinline__ void rhs_eval(const double (&z)[NSL], double P10, dou
     double *__restrict__ piece = L.piece;
 
     wave_sync();   // previous evaluation's readers of C are done
+    double Ck[NSL];
 #pragma unroll
     for (int s = 0; s < NSL; ++s) {
         const int k = s * G + go;
-        if (k >= 1 && k < N) C[k - 1] = rho * z[s] * invW[s];
+        Ck[s] = (k >= 1 && k < N) ? rho * z[s] * invW[s] : 0.0;
+        if (k >= 1 && k < N) C[k - 1] = Ck[s];
+    }
+    // third-body concentration of each efficiency set, [M] = sum_i alpha_i C_i
+    if constexpr (PD)
+    for (int q = 0; q < NMS; ++q) {
+        double part = 0.0;
+#pragma unroll
+        for (int s = 0; s < NSL; ++s) part += L.eff[q * NK + s * G + go] * Ck[s];
+        part = gsum<G>(part);
+        if (g == 0) L.Mv[q] = part;
     }
     wave_sync();
 
@@ -395,7 +443,8 @@ __device__ __forceinline__ void rhs_eval(const double (&z)[NSL], double P10, dou
         // follow the table in LDS and is not used.
         const double2 *ub = reinterpret_cast<const double2 *>(L.units) + g;
         double2 u3n = ub[3 * G];
-        for (int r = 0; r < RU; ++r) {
+        const int r_fast = PD ? RUp : RU;
+        for (int r = 0; r < r_fast; ++r) {
             const int p = r * G + g;
             const double2 *u = ub + (size_t)(4 * r) * G;
             // reactant slots first: the concentration products load and
@@ -412,6 +461,50 @@ __device__ __forceinline__ void rhs_eval(const double (&z)[NSL], double P10, dou
             const double cr = cat(b, 0) * cat(b, 1) * cat(b, 2);
             const double kf = exp_cw(u0.x + u0.y * lnT - u1.x * invT);
             const double kr = exp_cw(u1.y + u2.x * lnT - u2.y * invT);
+            Q[p] = kf * cf - kr * cr;
+        }
+        // rounds with pressure-dependent units: third body and falloff (only
+        // in the kernels built for mechanisms that have them)
+        if constexpr (PD)
+        for (int r = RUp; r < RU; ++r) {
+            const int p = r * G + g;
+            const double2 *u = ub + (size_t)(4 * r) * G;
+            const double2 u0 = u[0], u1 = u[G], u2 = u[2 * G], u3 = u[3 * G];
+            const uint64_t a = __double_as_longlong(u3.x), b = __double_as_longlong(u3.y);
+            const unsigned char *Cb = reinterpret_cast<const unsigned char *>(C);
+            auto cat = [&](uint64_t o, int sl) {
+                return *reinterpret_cast<const double *>(Cb + ((o >> (16 * sl)) & 0xffffu));
+            };
+            const double cf = cat(a, 0) * cat(a, 1) * cat(a, 2);
+            const double cr = cat(b, 0) * cat(b, 1) * cat(b, 2);
+            double kf = exp_cw(u0.x + u0.y * lnT - u1.x * invT);
+            double kr = exp_cw(u1.y + u2.x * lnT - u2.y * invT);
+            const double2 *pd = reinterpret_cast<const double2 *>(L.pdep) +
+                                (size_t)(6 * (r - RUp)) * G + g;
+            const double2 d0 = pd[0];
+            const uint64_t tag = __double_as_longlong(d0.x);
+            const int kind = (int)(tag & 0xffu);
+            if (kind != 0) {
+                const double M = L.Mv[(tag >> 8) & 0xffu];
+                if (kind == 1) {
+                    kf *= M;
+                    kr *= M;
+                } else {
+                    const double2 d1 = pd[G], d2 = pd[2 * G], d3 = pd[3 * G];
+                    const double k0f = exp_cw(d0.y + d1.x * lnT - d1.y * invT);
+                    const double k0r = exp_cw(d2.x + d2.y * lnT - d3.x * invT);
+                    double lFc = 0.0;   // log10 of the Troe centre value (Lindemann: F = 1)
+                    if (kind == 3) {
+                        const double2 d4 = pd[4 * G], d5 = pd[5 * G];
+                        const double Fc = (1.0 - d4.x) * exp_cw(-T * d4.y) +
+                                          d4.x * exp_cw(-T * d5.x) +
+                                          (d5.y > 0.0 ? exp_cw(-d5.y * invT) : 0.0);
+                        lFc = log_pos(Fc) * INV_LN10;
+                    }
+                    kf = falloff_rate(kf, k0f * M, lFc, kind == 3);
+                    kr = falloff_rate(kr, k0r * M, lFc, kind == 3);
+                }
+            }
             Q[p] = kf * cf - kr * cr;
         }
     }
@@ -463,22 +556,6 @@ __device__ __forceinline__ void rhs_eval(const double (&z)[NSL], double P10, dou
 
 // ---------------------------------------------------------------- staging
 
-__device__ __forceinline__ void stage_tables(const Params &p, int G, double *spec_l,
-                                             uint32_t *gather_l, int32_t *ps_l,
-                                             double *units_l, int n_units_l) {
-    const int tid = threadIdx.x, nt = blockDim.x;
-    for (int i = tid; i < NFIELD * p.NK; i += nt) spec_l[i] = p.tab.spec[i];
-    for (int i = tid; i < p.NSEG * (p.SEGL / 2) * G; i += nt) gather_l[i] = p.tab.gather[i];
-    for (int i = tid; i <= 2 * p.NK; i += nt) ps_l[i] = p.tab.ps[i];
-    // unit records, lane-interleaved in 16-byte pieces (see rhs_eval)
-    const double2 *ug = reinterpret_cast<const double2 *>(p.tab.units);
-    double2 *ul = reinterpret_cast<double2 *>(units_l);
-    for (int i = tid; i < n_units_l * (UNIT_DOUBLES / 2); i += nt) {
-        const int unit = i / (UNIT_DOUBLES / 2), q = i % (UNIT_DOUBLES / 2);
-        ul[((unit / G) * (UNIT_DOUBLES / 2) + q) * G + unit % G] = ug[i];
-    }
-}
-
 template <int RUC>
 __device__ __forceinline__ void load_unit_regs(const Params &p, UnitRegs<RUC> &ur, int g, int G) {
     if constexpr (RUC > 0) {
@@ -503,58 +580,94 @@ __device__ __forceinline__ void load_unit_regs(const Params &p, UnitRegs<RUC> &u
 // Bytes of per-group control state kept in LDS by the integrator kernels.
 constexpr int STATE_BYTES = 320;
 
+// Sizes that fix the LDS layout of a workgroup.
+struct Shape {
+    int NK, RU, G, NSEG, SEGL, NPR, NMS;
+    bool units_in_lds;
+};
+
+__device__ __forceinline__ Shape shape_of(const Params &p, int G, bool units_in_lds) {
+    return Shape{p.NK, p.RU, G, p.NSEG, p.SEGL, p.NPR, p.NMS, units_in_lds};
+}
+
 // Doubles of per-group LDS: concentrations, net rates (+ zero slot, padded to
-// even), gather pieces.
-__host__ __device__ inline size_t group_doubles(int NK, int RU, int G, int NSEG) {
-    return (size_t)NK + (size_t)RU * G + 2 + (size_t)NSEG * G;
+// even), gather pieces, third-body concentrations of the efficiency sets
+// (padded to even).
+__host__ __device__ inline size_t group_doubles(const Shape &s) {
+    return (size_t)s.NK + (size_t)s.RU * s.G + 2 + (size_t)s.NSEG * s.G + (size_t)((s.NMS + 1) & ~1);
 }
 
 // Bytes of dynamic LDS for a workgroup of `groups` groups.
-__host__ __device__ inline size_t lds_bytes(int NK, int RU, int G, int NSEG, int SEGL, int groups,
-                                            bool units_in_lds) {
-    size_t b = (size_t)NFIELD * NK * 8;
-    if (units_in_lds) b += (size_t)RU * G * UNIT_DOUBLES * 8;
-    b += (size_t)groups * group_doubles(NK, RU, G, NSEG) * 8;
+__host__ __device__ inline size_t lds_bytes(const Shape &s, int groups) {
+    size_t b = (size_t)NFIELD * s.NK * 8;
+    if (s.units_in_lds) b += (size_t)s.RU * s.G * UNIT_DOUBLES * 8;
+    b += (size_t)s.NPR * s.G * PDEP_DOUBLES * 8;
+    b += (size_t)s.NMS * s.NK * 8;
+    b += (size_t)groups * group_doubles(s) * 8;
     b += (size_t)groups * STATE_BYTES;
-    b += (size_t)NSEG * (SEGL / 2) * G * 4 + ((size_t)2 * NK + 1) * 4;
+    b += (size_t)s.NSEG * (s.SEGL / 2) * s.G * 4 + ((size_t)2 * s.NK + 1) * 4;
     return b;
 }
 
 struct LdsPtrs {
-    double *spec, *units;
+    double *spec, *units, *pdep, *eff;
     uint32_t *gather;
     int32_t *ps;
     double *groups;
     unsigned char *states;
 };
 
-__device__ __forceinline__ LdsPtrs carve(unsigned char *base, int NK, int RU, int G, int NSEG,
-                                         int SEGL, int groups, bool units_in_lds) {
+__device__ __forceinline__ LdsPtrs carve(unsigned char *base, const Shape &s, int groups) {
     LdsPtrs l;
     size_t off = 0;
-    l.spec = reinterpret_cast<double *>(base + off); off += (size_t)NFIELD * NK * 8;
+    l.spec = reinterpret_cast<double *>(base + off); off += (size_t)NFIELD * s.NK * 8;
     l.units = reinterpret_cast<double *>(base + off);
-    if (units_in_lds) off += (size_t)RU * G * UNIT_DOUBLES * 8;
+    if (s.units_in_lds) off += (size_t)s.RU * s.G * UNIT_DOUBLES * 8;
+    l.pdep = reinterpret_cast<double *>(base + off); off += (size_t)s.NPR * s.G * PDEP_DOUBLES * 8;
+    l.eff = reinterpret_cast<double *>(base + off); off += (size_t)s.NMS * s.NK * 8;
     l.groups = reinterpret_cast<double *>(base + off);
-    off += (size_t)groups * group_doubles(NK, RU, G, NSEG) * 8;
+    off += (size_t)groups * group_doubles(s) * 8;
     l.states = base + off;
     off += (size_t)groups * STATE_BYTES;
-    l.gather = reinterpret_cast<uint32_t *>(base + off); off += (size_t)NSEG * (SEGL / 2) * G * 4;
+    l.gather = reinterpret_cast<uint32_t *>(base + off); off += (size_t)s.NSEG * (s.SEGL / 2) * s.G * 4;
     l.ps = reinterpret_cast<int32_t *>(base + off);
     return l;
 }
 
 // Per-group LDS views and their one-time initialisation (absent-slot
 // concentration 1.0, the zero slot of the signed rates).
-__device__ __forceinline__ GroupLds group_view(const LdsPtrs &lp, const Params &p, int G,
-                                               int gib) {
+__device__ __forceinline__ GroupLds group_view(const LdsPtrs &lp, const Shape &s, int gib) {
     GroupLds L;
     L.spec = lp.spec; L.gather = lp.gather; L.ps = lp.ps;
     L.units = lp.units;
-    L.C = lp.groups + (size_t)gib * group_doubles(p.NK, p.RU, G, p.NSEG);
-    L.Q = L.C + p.NK;
-    L.piece = L.Q + p.RU * G + 2;
+    L.pdep = lp.pdep;
+    L.eff = lp.eff;
+    L.C = lp.groups + (size_t)gib * group_doubles(s);
+    L.Q = L.C + s.NK;
+    L.piece = L.Q + s.RU * s.G + 2;
+    L.Mv = L.piece + s.NSEG * s.G;
     return L;
+}
+
+__device__ __forceinline__ void stage_tables(const Params &p, int G, const LdsPtrs &lp,
+                                             int n_units_l) {
+    double *spec_l = lp.spec, *units_l = lp.units;
+    uint32_t *gather_l = lp.gather;
+    int32_t *ps_l = lp.ps;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    // pressure-dependent records (already interleaved) and efficiency sets
+    for (int i = tid; i < p.NPR * G * PDEP_DOUBLES; i += nt) lp.pdep[i] = p.tab.pdep[i];
+    for (int i = tid; i < p.NMS * p.NK; i += nt) lp.eff[i] = p.tab.eff[i];
+    for (int i = tid; i < NFIELD * p.NK; i += nt) spec_l[i] = p.tab.spec[i];
+    for (int i = tid; i < p.NSEG * (p.SEGL / 2) * G; i += nt) gather_l[i] = p.tab.gather[i];
+    for (int i = tid; i <= 2 * p.NK; i += nt) ps_l[i] = p.tab.ps[i];
+    // unit records, lane-interleaved in 16-byte pieces (see rhs_eval)
+    const double2 *ug = reinterpret_cast<const double2 *>(p.tab.units);
+    double2 *ul = reinterpret_cast<double2 *>(units_l);
+    for (int i = tid; i < n_units_l * (UNIT_DOUBLES / 2); i += nt) {
+        const int unit = i / (UNIT_DOUBLES / 2), q = i % (UNIT_DOUBLES / 2);
+        ul[((unit / G) * (UNIT_DOUBLES / 2) + q) * G + unit % G] = ug[i];
+    }
 }
 
 __device__ __forceinline__ void group_init(const GroupLds &L, const Params &p, int G, int g) {
@@ -574,15 +687,16 @@ struct Occ {
     static constexpr int threads = waves * 256;
 };
 
-template <int G, int NSL, int RUC>
+template <int G, int NSL, int RUC, bool PD>
 __global__ __launch_bounds__((Occ<RUC, NSL>::threads), (Occ<RUC, NSL>::waves)) void rhs_kernel(Params p) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int groups = blockDim.x / G;
     const int gib = threadIdx.x / G;
     const int g = threadIdx.x % G;
-    LdsPtrs lp = carve(lds_raw, p.NK, p.RU, G, p.NSEG, p.SEGL, groups, RUC == 0);
-    stage_tables(p, G, lp.spec, lp.gather, lp.ps, lp.units, RUC == 0 ? p.RU * G : 0);
-    GroupLds L = group_view(lp, p, G, gib);
+    const Shape sh = shape_of(p, G, RUC == 0);
+    LdsPtrs lp = carve(lds_raw, sh, groups);
+    stage_tables(p, G, lp, RUC == 0 ? p.RU * G : 0);
+    GroupLds L = group_view(lp, sh, gib);
     group_init(L, p, G, g);
     __syncthreads();
     UnitRegs<RUC> ur;
@@ -603,7 +717,8 @@ __global__ __launch_bounds__((Occ<RUC, NSL>::threads), (Occ<RUC, NSL>::waves)) v
     }
     if (!active) z[0] = (g == 0) ? 1000.0 : z[0];
     const double P10 = active ? p.P[cell] * 10.0 : 1e6;
-    rhs_eval<G, NSL, RUC>(z, P10, 1.0 / P10, fz, L, ur, g, p.N, p.RU, p.NSEG, p.SEGL);
+    rhs_eval<G, NSL, RUC, PD>(z, P10, 1.0 / P10, fz, L, ur, g, p.N, p.RU, p.NSEG, p.SEGL, p.RUp,
+                              p.NMS);
     if (active) {
 #pragma unroll
         for (int s = 0; s < NSL; ++s) {

@@ -24,9 +24,12 @@ constexpr double LNA_ZERO = -1e4;          // ln A of a reaction whose rate is i
 // laid out with stride NK, the gather is balanced over G lanes.
 struct NkTables {
     int G = 0, NK = 0, RU = 0, NSEG = 0, SEGL = 0;
+    int RUp = 0, NPR = 0, NMS = 0;   // pressure-dependent rounds and efficiency sets
     double *spec = nullptr;
     uint32_t *gather = nullptr;
     int32_t *ps = nullptr;
+    double *pdep = nullptr;          // [NPR * G][12], lane-interleaved
+    double *eff = nullptr;           // [NMS][NK]
 };
 
 }  // namespace
@@ -43,6 +46,10 @@ struct rkc_mech {
     int device = 0;
     int nS = 0, nR = 0, N = 0, nU = 0, nU_pad = 0, nnz = 0, max_row = 0;
     std::vector<double> units_h;                       // [nU_pad][8]
+    int n_plain = 0, n_pdep = 0;                       // units [0, n_plain) plain, then pdep
+    std::vector<double> pdep_h;                        // [n_pdep][PDEP_DOUBLES]
+    std::vector<std::vector<double>> effsets;          // distinct efficiency vectors [nS]
+    double *pdep_d = nullptr;
     std::vector<double> W, lo, hi, Tmid;               // species data
     std::vector<std::vector<std::pair<int, int>>> rows;  // species -> (unit, dnu)
     double *units_d = nullptr;
@@ -271,6 +278,29 @@ int ensure_tables(rkc_mech *m, int G, int NK, int RU, NkTables **out) {
     t.RU = RU;
     t.NSEG = gp.NSEG;
     t.SEGL = gp.SEGL;
+    // rounds from RUp on hold the pressure-dependent units (plain ones first)
+    t.NMS = (int)m->effsets.size();
+    t.RUp = m->n_pdep > 0 ? m->n_plain / G : RU;
+    t.NPR = RU - t.RUp;
+    std::vector<double> pd((size_t)t.NPR * G * rkcdev::PDEP_DOUBLES, 0.0);
+    for (int l = 0; l < t.NPR * G; ++l) {
+        const int unit = t.RUp * G + l;
+        if (unit < m->n_plain || unit >= m->nU) continue;
+        const double *src = &m->pdep_h[(size_t)(unit - m->n_plain) * rkcdev::PDEP_DOUBLES];
+        const int r = l / G, g = l % G;
+        for (int q = 0; q < rkcdev::PDEP_DOUBLES / 2; ++q) {
+            const size_t at = ((size_t)(r * (rkcdev::PDEP_DOUBLES / 2) + q) * G + g) * 2;
+            pd[at] = src[2 * q];
+            pd[at + 1] = src[2 * q + 1];
+        }
+    }
+    std::vector<double> ef((size_t)t.NMS * NK, 0.0);
+    for (int q = 0; q < t.NMS; ++q)
+        for (int i = 0; i < nS; ++i) ef[(size_t)q * NK + i + 1] = m->effsets[q][i];
+    if (!pd.empty() && hipMalloc(&t.pdep, pd.size() * 8) != hipSuccess) return RKC_ENOMEM;
+    if (!ef.empty() && hipMalloc(&t.eff, ef.size() * 8) != hipSuccess) return RKC_ENOMEM;
+    if (!pd.empty()) HIP_OK(hipMemcpy(t.pdep, pd.data(), pd.size() * 8, hipMemcpyHostToDevice));
+    if (!ef.empty()) HIP_OK(hipMemcpy(t.eff, ef.data(), ef.size() * 8, hipMemcpyHostToDevice));
     if (hipMalloc(&t.spec, spec.size() * 8) != hipSuccess) return RKC_ENOMEM;
     if (hipMalloc(&t.gather, gp.words.size() * 4) != hipSuccess ||
         hipMalloc(&t.ps, gp.ps.size() * 4) != hipSuccess) {
@@ -309,7 +339,8 @@ int choose_variant(const rkc_mech *m, int lanes, int placement, Choice *out) {
         if (tab[i].NSL >= nsl_need) best_nsl = std::min(best_nsl, tab[i].NSL);
     if (best_nsl == (1 << 30)) return RKC_ENOTSUP;
     const rkchost::VariantDesc *pick = nullptr;
-    if (placement == RKC_PARAMS_REGISTERS)
+    // register-resident parameters cover plain units only
+    if (placement == RKC_PARAMS_REGISTERS && m->n_pdep == 0)
         for (int i = 0; i < n; ++i)
             if (tab[i].NSL == best_nsl && tab[i].RUC == ru) pick = &tab[i];
     if (!pick)
@@ -349,9 +380,8 @@ int plan_launch(const rkc_mech *m, const Choice &ch, const void *kernel, size_t 
     const int max_threads = ch.v.max_threads;
     int gpb = o.block_groups > 0 ? o.block_groups : std::max(1, max_threads / G);
     if (gpb * G > max_threads) gpb = max_threads / G;
-    auto need = [&](int groups) {
-        return rkcdev::lds_bytes(NK, ch.RU, G, nk->NSEG, nk->SEGL, groups, ch.v.RUC == 0);
-    };
+    const rkcdev::Shape sh{NK, ch.RU, G, nk->NSEG, nk->SEGL, nk->NPR, nk->NMS, ch.v.RUC == 0};
+    auto need = [&](int groups) { return rkcdev::lds_bytes(sh, groups); };
     while (gpb > 1 && need(gpb) > m->max_lds) --gpb;
     if (need(gpb) > m->max_lds) return RKC_ENOTSUP;
     L->groups_per_block = gpb;
@@ -395,6 +425,11 @@ void fill_params(const rkc_mech *m, const Choice &ch, const NkTables *nk, rkcdev
     p->tab.spec = nk->spec;
     p->tab.gather = nk->gather;
     p->tab.ps = nk->ps;
+    p->tab.pdep = nk->pdep;
+    p->tab.eff = nk->eff;
+    p->RUp = nk->RUp;
+    p->NPR = nk->NPR;
+    p->NMS = nk->NMS;
     p->agg = m->agg_d;
     p->queue = m->queue_d;
     p->coef = m->coef_d;
@@ -445,7 +480,10 @@ int enqueue_integrate(rkc_mech *m, size_t n, double *Td, const double *Pd, doubl
     NkTables *nk = nullptr;
     rc = ensure_tables(m, ch.v.G, ch.v.NSL * ch.v.G, ch.RU, &nk);
     if (rc) return rc;
-    const void *kernel = o.method == RKC_METHOD_RKC ? ch.v.k_rkc : ch.v.k_rkck;
+    const bool pd = m->n_pdep > 0;
+    const void *kernel = o.method == RKC_METHOD_RKC ? (pd ? ch.v.k_rkc_pd : ch.v.k_rkc)
+                                                    : (pd ? ch.v.k_rkck_pd : ch.v.k_rkck);
+    if (!kernel) return RKC_ENOTSUP;
     Launch L;
     rc = plan_launch(m, ch, kernel, n, o, true, nk, &L);
     if (rc) return rc;
@@ -493,7 +531,9 @@ int prepare(rkc_mech *m, const rkc_opts &o, size_t n_cells) {
     if (rc || n_cells == 0) return rc;
     // sets the kernels' dynamic-LDS limit now rather than inside a capture
     Launch L;
-    for (const void *k : {ch.v.k_rkc, ch.v.k_rkck}) {
+    const bool pd = m->n_pdep > 0;
+    for (const void *k : {pd ? ch.v.k_rkc_pd : ch.v.k_rkc, pd ? ch.v.k_rkck_pd : ch.v.k_rkck}) {
+        if (!k) return RKC_ENOTSUP;
         rc = plan_launch(m, ch, k, n_cells, o, true, nk, &L);
         if (rc) return rc;
     }
@@ -556,10 +596,13 @@ int rkc_mech_destroy(rkc_mech *m) {
         (void)hipFree(t.spec);
         (void)hipFree(t.gather);
         (void)hipFree(t.ps);
+        if (t.pdep) (void)hipFree(t.pdep);
+        if (t.eff) (void)hipFree(t.eff);
     }
     if (m->agg_d) (void)hipFree(m->agg_d);
     if (m->queue_d) (void)hipFree(m->queue_d);
     if (m->coef_d) (void)hipFree(m->coef_d);
+    if (m->pdep_d) (void)hipFree(m->pdep_d);
     if (m->stage_d) (void)hipFree(m->stage_d);
     (void)hipSetDevice(dev);
     delete m;
@@ -581,6 +624,26 @@ int rkc_mech_create(const rkc_mech_desc *d, rkc_mech **out) {
             if (!std::isfinite(d->nasa_low[7 * i + q]) || !std::isfinite(d->nasa_high[7 * i + q]))
                 return RKC_EINVAL;
     }
+    for (int j = 0; j < nR && d->pdep; ++j) {
+        const int kind = d->pdep[j];
+        if (kind < RKC_PDEP_PLAIN || kind > RKC_PDEP_TROE) return RKC_EINVAL;
+        if (kind != RKC_PDEP_PLAIN && d->eff)
+            for (int i = 0; i < nS; ++i)
+                if (!(d->eff[(size_t)j * nS + i] >= 0.0) || !std::isfinite(d->eff[(size_t)j * nS + i]))
+                    return RKC_EINVAL;
+        if (kind >= RKC_PDEP_LINDEMANN) {
+            if (!d->A0 || !d->beta0 || !d->Ea0) return RKC_EINVAL;
+            if (!(d->A0[j] >= 0.0) || !std::isfinite(d->A0[j]) || !std::isfinite(d->beta0[j]) ||
+                !std::isfinite(d->Ea0[j]))
+                return RKC_EINVAL;
+        }
+        if (kind == RKC_PDEP_TROE) {
+            if (!d->troe) return RKC_EINVAL;
+            const double *t = d->troe + 4 * (size_t)j;
+            if (!std::isfinite(t[0]) || !(t[1] > 0.0) || !(t[2] > 0.0) || !std::isfinite(t[3]))
+                return RKC_EINVAL;
+        }
+    }
     for (int j = 0; j < nR; ++j) {
         if (!(d->A[j] >= 0.0) || !std::isfinite(d->A[j]) || !std::isfinite(d->beta[j]) ||
             !std::isfinite(d->Ea[j]))
@@ -601,39 +664,98 @@ int rkc_mech_create(const rkc_mech_desc *d, rkc_mech **out) {
     m->Tmid.assign(d->T_mid, d->T_mid + nS);
     m->rows.assign(nS, {});
 
-    // Reaction units: a reaction immediately followed by its exact reverse is
-    // one unit with net rate of progress; any other reaction is a unit alone.
-    std::vector<double> units;
-    int p = 0;
-    for (int j = 0; j < nR; ++p) {
+    // Reaction units: a reaction immediately followed by its exact reverse
+    // (with the same pressure dependence) is one unit with net rate of
+    // progress; any other reaction is a unit alone.  Plain units come first,
+    // then the pressure-dependent ones by kind, so that the kernels' unit
+    // rounds are uniform except for a few.
+    struct UnitSrc {
+        double rec[UNIT_DOUBLES];
+        double pd[rkcdev::PDEP_DOUBLES];
+        int kind;
+        std::vector<std::pair<int, int>> dnu;   // (species, nu'' - nu')
+    };
+    auto kind_of = [&](int j) { return d->pdep ? d->pdep[j] : RKC_PDEP_PLAIN; };
+    auto eff_row = [&](int j) {
+        std::vector<double> e(nS, 1.0);
+        if (d->eff) e.assign(d->eff + (size_t)j * nS, d->eff + (size_t)(j + 1) * nS);
+        return e;
+    };
+    std::vector<UnitSrc> srcs;
+    for (int j = 0; j < nR;) {
         const int32_t *rf = d->reac + 3 * j, *pf = d->prod + 3 * j;
-        const bool pair = (j + 1 < nR) && same_multiset(d->reac + 3 * (j + 1), pf) &&
-                          same_multiset(d->prod + 3 * (j + 1), rf);
-        double rec[UNIT_DOUBLES] = {0};
-        rec[0] = ln_a(d->A[j]);
-        rec[1] = d->beta[j];
-        rec[2] = d->Ea[j] / R_J;
+        const int kind = kind_of(j);
+        bool pair = (j + 1 < nR) && same_multiset(d->reac + 3 * (j + 1), pf) &&
+                    same_multiset(d->prod + 3 * (j + 1), rf) && kind_of(j + 1) == kind;
+        if (pair && kind != RKC_PDEP_PLAIN) pair = eff_row(j) == eff_row(j + 1);
+        if (pair && kind == RKC_PDEP_TROE)
+            pair = std::equal(d->troe + 4 * (size_t)j, d->troe + 4 * (size_t)j + 4,
+                              d->troe + 4 * (size_t)(j + 1));
+        UnitSrc u;
+        std::memset(u.rec, 0, sizeof(u.rec));
+        std::memset(u.pd, 0, sizeof(u.pd));
+        u.kind = kind;
+        u.rec[0] = ln_a(d->A[j]);
+        u.rec[1] = d->beta[j];
+        u.rec[2] = d->Ea[j] / R_J;
         uint64_t idr = 0;
+        const int32_t none[3] = {-1, -1, -1};
         if (pair) {
-            rec[3] = ln_a(d->A[j + 1]);
-            rec[4] = d->beta[j + 1];
-            rec[5] = d->Ea[j + 1] / R_J;
+            u.rec[3] = ln_a(d->A[j + 1]);
+            u.rec[4] = d->beta[j + 1];
+            u.rec[5] = d->Ea[j + 1] / R_J;
             idr = pack_slots(d->reac + 3 * (j + 1), nS);
         } else {
-            rec[3] = LNA_ZERO;
-            const int32_t none[3] = {-1, -1, -1};
+            u.rec[3] = LNA_ZERO;
             idr = pack_slots(none, nS);
         }
         const uint64_t idf = pack_slots(rf, nS);
-        std::memcpy(&rec[6], &idf, 8);
-        std::memcpy(&rec[7], &idr, 8);
-        units.insert(units.end(), rec, rec + UNIT_DOUBLES);
+        std::memcpy(&u.rec[6], &idf, 8);
+        std::memcpy(&u.rec[7], &idr, 8);
+        if (kind != RKC_PDEP_PLAIN) {
+            // efficiency set index
+            const std::vector<double> e = eff_row(j);
+            size_t q = 0;
+            while (q < m->effsets.size() && m->effsets[q] != e) ++q;
+            if (q == m->effsets.size()) m->effsets.push_back(e);
+            const uint64_t tag = (uint64_t)kind | ((uint64_t)q << 8);
+            std::memcpy(&u.pd[0], &tag, 8);
+            if (kind >= RKC_PDEP_LINDEMANN) {
+                u.pd[1] = ln_a(d->A0[j]);
+                u.pd[2] = d->beta0[j];
+                u.pd[3] = d->Ea0[j] / R_J;
+                u.pd[4] = pair ? ln_a(d->A0[j + 1]) : LNA_ZERO;
+                u.pd[5] = pair ? d->beta0[j + 1] : 0.0;
+                u.pd[6] = pair ? d->Ea0[j + 1] / R_J : 0.0;
+            }
+            if (kind == RKC_PDEP_TROE) {
+                const double *t = d->troe + 4 * (size_t)j;
+                u.pd[8] = t[0];
+                u.pd[9] = 1.0 / t[1];
+                u.pd[10] = 1.0 / t[2];
+                u.pd[11] = t[3];
+            }
+        }
         for (int i = 0; i < nS; ++i) {
             const int dnu = count_in(pf, i) - count_in(rf, i);
-            if (dnu != 0) m->rows[i].push_back({p, dnu});
+            if (dnu != 0) u.dnu.push_back({i, dnu});
         }
+        srcs.push_back(u);
         j += pair ? 2 : 1;
     }
+    std::stable_sort(srcs.begin(), srcs.end(),
+                     [](const UnitSrc &x, const UnitSrc &y) { return x.kind < y.kind; });
+    if (m->effsets.size() > (size_t)rkcdev::MAX_EFFSETS) { delete m; return RKC_ENOTSUP; }
+    std::vector<double> units;
+    int p = 0;
+    for (const UnitSrc &u : srcs) {
+        units.insert(units.end(), u.rec, u.rec + UNIT_DOUBLES);
+        if (u.kind != RKC_PDEP_PLAIN) m->pdep_h.insert(m->pdep_h.end(), u.pd, u.pd + rkcdev::PDEP_DOUBLES);
+        else ++m->n_plain;
+        for (const auto &e : u.dnu) m->rows[e.first].push_back({p, e.second});
+        ++p;
+    }
+    m->n_pdep = p - m->n_plain;
     m->nU = p;
     m->nU_pad = std::max(64, (p + 63) / 64 * 64);
     if (m->nU_pad >= (1 << 23)) { delete m; return RKC_ENOTSUP; }
@@ -667,6 +789,13 @@ int rkc_mech_create(const rkc_mech_desc *d, rkc_mech **out) {
         else if (hipMemcpy(m->units_d, m->units_h.data(), m->units_h.size() * 8,
                            hipMemcpyHostToDevice) != hipSuccess)
             rc = RKC_EDEVICE;
+        if (rc == RKC_OK && m->n_pdep > 0) {
+            if (hipMalloc(&m->pdep_d, m->pdep_h.size() * 8) != hipSuccess)
+                rc = RKC_ENOMEM;
+            else if (hipMemcpy(m->pdep_d, m->pdep_h.data(), m->pdep_h.size() * 8,
+                               hipMemcpyHostToDevice) != hipSuccess)
+                rc = RKC_EDEVICE;
+        }
         if (rc == RKC_OK) {
             const std::vector<double> ct = coef_table();
             if (hipMalloc(&m->coef_d, ct.size() * 8) != hipSuccess)
@@ -731,7 +860,9 @@ int rkc_rhs(const rkc_mech *mc, size_t n, const double *T, const double *P, cons
     rkc_opts lo = o;
     lo.schedule = RKC_SCHED_PLAIN;
     Launch L;
-    rc = plan_launch(m, ch, ch.v.k_rhs, n, lo, false, nk, &L);
+    const void *krhs = m->n_pdep > 0 ? ch.v.k_rhs_pd : ch.v.k_rhs;
+    if (!krhs) return RKC_ENOTSUP;
+    rc = plan_launch(m, ch, krhs, n, lo, false, nk, &L);
     if (rc) return rc;
     rkcdev::Params p;
     fill_params(m, ch, nk, &p);
@@ -741,7 +872,7 @@ int rkc_rhs(const rkc_mech *mc, size_t n, const double *T, const double *P, cons
     p.Y = const_cast<double *>(Yd);
     p.F = fd;
     void *args[] = {&p};
-    HIP_OK(hipLaunchKernel(ch.v.k_rhs, dim3(L.blocks), dim3(L.threads), args, L.lds, st));
+    HIP_OK(hipLaunchKernel(krhs, dim3(L.blocks), dim3(L.threads), args, L.lds, st));
     if (!o.device_ptrs) {
         HIP_OK(hipMemcpyAsync(f, fd, 8 * n * N, hipMemcpyDeviceToHost, st));
         HIP_OK(hipStreamSynchronize(st));

@@ -160,9 +160,10 @@ __device__ __forceinline__ double rms_norm(const double (&d)[NSL], const double 
     const int groups = blockDim.x / G;                                                       \
     const int gib = threadIdx.x / G;                                                         \
     const int g = threadIdx.x % G;                                                           \
-    LdsPtrs lp = carve(lds_raw, p.NK, p.RU, G, p.NSEG, p.SEGL, groups, RUC == 0);            \
-    stage_tables(p, G, lp.spec, lp.gather, lp.ps, lp.units, RUC == 0 ? p.RU * G : 0);        \
-    GroupLds L = group_view(lp, p, G, gib);                                                  \
+    const Shape sh = shape_of(p, G, RUC == 0);                                               \
+    LdsPtrs lp = carve(lds_raw, sh, groups);                                                 \
+    stage_tables(p, G, lp, RUC == 0 ? p.RU * G : 0);                                         \
+    GroupLds L = group_view(lp, sh, gib);                                                    \
     group_init(L, p, G, g);                                                                  \
     __syncthreads();                                                                         \
     UnitRegs<RUC> ur;                                                                        \
@@ -189,7 +190,7 @@ enum { ACT_NONE = 0, ACT_BEGIN_STEP, ACT_AFTER_SIGMA, ACT_POWER_INIT, ACT_POWER_
 
 // ------------------------------------------------------------------- RKC
 
-template <int G, int NSL, int RUC>
+template <int G, int NSL, int RUC, bool PD>
 __global__ __launch_bounds__((Occ<RUC, NSL>::threads), (Occ<RUC, NSL>::waves)) void rkc_kernel(Params p) {
     RKC_KERNEL_PROLOGUE
     const double sqrt_u = sqrt(u_round);
@@ -237,7 +238,8 @@ __global__ __launch_bounds__((Occ<RUC, NSL>::threads), (Occ<RUC, NSL>::waves)) v
     for (;;) {
         if (!__any(S.cell >= 0)) break;   // a wave whose groups hold no cell issues nothing
         ++iters;
-        rhs_eval<G, NSL, RUC>(z, S.P10, S.invP10, fz, L, ur, g, N, p.RU, p.NSEG, p.SEGL);
+        rhs_eval<G, NSL, RUC, PD>(z, S.P10, S.invP10, fz, L, ur, g, N, p.RU, p.NSEG, p.SEGL,
+                                  p.RUp, p.NMS);
         if (S.cell >= 0) {
             Counts c = S.c;
             c.n_rhs += 1;
@@ -554,7 +556,7 @@ struct RkckState {
 };
 static_assert(sizeof(RkckState) <= STATE_BYTES, "RKCK state exceeds its LDS slot");
 
-template <int G, int NSL, int RUC>
+template <int G, int NSL, int RUC, bool PD>
 __global__ __launch_bounds__((Occ<RUC, NSL>::threads), (Occ<RUC, NSL>::waves)) void rkck_kernel(Params p) {
     RKC_KERNEL_PROLOGUE
     RkckState &S = *reinterpret_cast<RkckState *>(lp.states + (size_t)gib * STATE_BYTES);
@@ -601,7 +603,8 @@ __global__ __launch_bounds__((Occ<RUC, NSL>::threads), (Occ<RUC, NSL>::waves)) v
     for (;;) {
         if (!__any(S.cell >= 0)) break;   // a wave whose groups hold no cell issues nothing
         ++iters;
-        rhs_eval<G, NSL, RUC>(z, S.P10, S.invP10, fz, L, ur, g, N, p.RU, p.NSEG, p.SEGL);
+        rhs_eval<G, NSL, RUC, PD>(z, S.P10, S.invP10, fz, L, ur, g, N, p.RU, p.NSEG, p.SEGL,
+                                  p.RUp, p.NMS);
         if (S.cell >= 0) {
             Counts c = S.c;
             c.n_rhs += 1;

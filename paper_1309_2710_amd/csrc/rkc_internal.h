@@ -17,6 +17,10 @@ struct VariantDesc {
     const void *k_rkc;
     const void *k_rkck;
     const void *k_rhs;
+    // the same kernels with the third-body/falloff rounds (null: not built)
+    const void *k_rkc_pd;
+    const void *k_rkck_pd;
+    const void *k_rhs_pd;
 };
 
 const VariantDesc *variants_g64(int *n);
@@ -64,10 +68,24 @@ void fill_stats(const unsigned long long *agg, const LaunchInfo &li, rkc_stats *
 
 }  // namespace rkchost
 
+// A variant with plain-reaction kernels only (register-resident parameters).
 #define RKC_VARIANT(G_, NSL_, RUC_)                                                            \
     rkchost::VariantDesc {                                                                     \
-        G_, NSL_, RUC_, (rkcdev::Occ<RUC_, NSL_>::threads),                                          \
-            reinterpret_cast<const void *>(&rkcdev::rkc_kernel<G_, NSL_, RUC_>),               \
-            reinterpret_cast<const void *>(&rkcdev::rkck_kernel<G_, NSL_, RUC_>),              \
-            reinterpret_cast<const void *>(&rkcdev::rhs_kernel<G_, NSL_, RUC_>)                \
+        G_, NSL_, RUC_, (rkcdev::Occ<RUC_, NSL_>::threads),                                    \
+            reinterpret_cast<const void *>(&rkcdev::rkc_kernel<G_, NSL_, RUC_, false>),        \
+            reinterpret_cast<const void *>(&rkcdev::rkck_kernel<G_, NSL_, RUC_, false>),       \
+            reinterpret_cast<const void *>(&rkcdev::rhs_kernel<G_, NSL_, RUC_, false>),        \
+            nullptr, nullptr, nullptr                                                          \
+    }
+
+// A variant with both kernel sets (parameters in LDS).
+#define RKC_VARIANT_PD(G_, NSL_)                                                               \
+    rkchost::VariantDesc {                                                                     \
+        G_, NSL_, 0, (rkcdev::Occ<0, NSL_>::threads),                                          \
+            reinterpret_cast<const void *>(&rkcdev::rkc_kernel<G_, NSL_, 0, false>),           \
+            reinterpret_cast<const void *>(&rkcdev::rkck_kernel<G_, NSL_, 0, false>),          \
+            reinterpret_cast<const void *>(&rkcdev::rhs_kernel<G_, NSL_, 0, false>),           \
+            reinterpret_cast<const void *>(&rkcdev::rkc_kernel<G_, NSL_, 0, true>),            \
+            reinterpret_cast<const void *>(&rkcdev::rkck_kernel<G_, NSL_, 0, true>),           \
+            reinterpret_cast<const void *>(&rkcdev::rhs_kernel<G_, NSL_, 0, true>)             \
     }

@@ -4,7 +4,7 @@
 
 namespace rkchost {
 
-static const VariantDesc kTable[] = {RKC_VARIANT(16, 1, 2), RKC_VARIANT(16, 1, 0), RKC_VARIANT(16, 2, 0)};
+static const VariantDesc kTable[] = {RKC_VARIANT(16, 1, 2), RKC_VARIANT_PD(16, 1), RKC_VARIANT_PD(16, 2)};
 
 const VariantDesc *variants_g16(int *n) {
     *n = (int)(sizeof(kTable) / sizeof(kTable[0]));

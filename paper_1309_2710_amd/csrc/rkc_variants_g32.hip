@@ -4,7 +4,7 @@
 
 namespace rkchost {
 
-static const VariantDesc kTable[] = {RKC_VARIANT(32, 1, 0), RKC_VARIANT(32, 2, 0)};
+static const VariantDesc kTable[] = {RKC_VARIANT_PD(32, 1), RKC_VARIANT_PD(32, 2)};
 
 const VariantDesc *variants_g32(int *n) {
     *n = (int)(sizeof(kTable) / sizeof(kTable[0]));

@@ -4,7 +4,7 @@
 
 namespace rkchost {
 
-static const VariantDesc kTable[] = {RKC_VARIANT(64, 1, 5), RKC_VARIANT(64, 1, 0), RKC_VARIANT(64, 2, 0), RKC_VARIANT(64, 4, 0)};
+static const VariantDesc kTable[] = {RKC_VARIANT(64, 1, 5), RKC_VARIANT_PD(64, 1), RKC_VARIANT_PD(64, 2), RKC_VARIANT_PD(64, 4)};
 
 const VariantDesc *variants_g64(int *n) {
     *n = (int)(sizeof(kTable) / sizeof(kTable[0]));

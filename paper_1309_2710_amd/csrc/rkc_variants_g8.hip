@@ -4,7 +4,7 @@
 
 namespace rkchost {
 
-static const VariantDesc kTable[] = {RKC_VARIANT(8, 2, 3), RKC_VARIANT(8, 2, 4), RKC_VARIANT(8, 2, 0), RKC_VARIANT(8, 4, 0)};
+static const VariantDesc kTable[] = {RKC_VARIANT(8, 2, 3), RKC_VARIANT(8, 2, 4), RKC_VARIANT_PD(8, 2), RKC_VARIANT_PD(8, 4)};
 
 const VariantDesc *variants_g8(int *n) {
     *n = (int)(sizeof(kTable) / sizeof(kTable[0]));

@@ -40,7 +40,12 @@ class MechDesc(ct.Structure):
     _fields_ = [("n_species", ct.c_int32), ("n_reactions", ct.c_int32),
                 ("W", ct.c_void_p), ("nasa_low", ct.c_void_p), ("nasa_high", ct.c_void_p),
                 ("T_mid", ct.c_void_p), ("reac", ct.c_void_p), ("prod", ct.c_void_p),
-                ("A", ct.c_void_p), ("beta", ct.c_void_p), ("Ea", ct.c_void_p)]
+                ("A", ct.c_void_p), ("beta", ct.c_void_p), ("Ea", ct.c_void_p),
+                ("pdep", ct.c_void_p), ("eff", ct.c_void_p), ("A0", ct.c_void_p),
+                ("beta0", ct.c_void_p), ("Ea0", ct.c_void_p), ("troe", ct.c_void_p)]
+
+
+PDEP_PLAIN, PDEP_THIRD_BODY, PDEP_LINDEMANN, PDEP_TROE = 0, 1, 2, 3
 
 
 class Opts(ct.Structure):
@@ -168,9 +173,18 @@ def _mech_desc(mech):
         "beta": np.ascontiguousarray(mech["beta"], np.float64),
         "Ea": np.ascontiguousarray(mech["Ea"], np.float64),
     }
+    opt = [None] * 6
+    if mech.get("pdep") is not None:
+        keep.update(pdep=np.ascontiguousarray(mech["pdep"], np.int32),
+                    eff=np.ascontiguousarray(mech["eff"], np.float64),
+                    A0=np.ascontiguousarray(mech["A0"], np.float64),
+                    beta0=np.ascontiguousarray(mech["beta0"], np.float64),
+                    Ea0=np.ascontiguousarray(mech["Ea0"], np.float64),
+                    troe=np.ascontiguousarray(mech["troe"], np.float64))
+        opt = [_np_ptr(keep[k]) for k in ["pdep", "eff", "A0", "beta0", "Ea0", "troe"]]
     d = MechDesc(nS, nR, *[_np_ptr(keep[k]) for k in
                            ["W", "nasa_low", "nasa_high", "T_mid", "reac", "prod", "A",
-                            "beta", "Ea"]])
+                            "beta", "Ea"]], *opt)
     return d, keep
 
 

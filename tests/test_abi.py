@@ -97,3 +97,18 @@ def test_binding_rejects_species_count_mismatch():
         rkc.integrate(FakeMech(), T, np.full(3, 1e5), np.zeros((4, 9)), 1e-6)
     with pytest.raises(ValueError):
         rkc.rhs(FakeMech(), T, P, np.zeros((4, 10)))
+
+
+def test_mech_create_rejects_bad_pressure_dependence_without_a_device():
+    from tests.test_oracle_pdep import _pdep
+    from tests import mechs
+    L = rkc.lib()
+    for kinds, troe in (([7], None), ([3], [[0.5, 0.0, 100.0, 0.0]]), ([3], [[0.5, 100.0, -1.0, 0.0]])):
+        m = _pdep(mechs.a_to_b(1e5, 10.0), kinds, k0=[1e10], troe=troe)
+        d, keep = rkc._mech_desc(m)
+        h = ct.c_void_p()
+        assert L.rkc_mech_create(ct.byref(d), ct.byref(h)) == rkc.EINVAL
+    m = _pdep(mechs.a_to_b(1e5, 10.0), [1], eff=[[1.0, -0.5]])
+    d, keep = rkc._mech_desc(m)
+    h = ct.c_void_p()
+    assert L.rkc_mech_create(ct.byref(d), ct.byref(h)) == rkc.EINVAL
