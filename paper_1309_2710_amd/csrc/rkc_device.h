@@ -143,8 +143,16 @@ __device__ __forceinline__ double readlane_f64(double x, int lane) {
 // a + b in one lane and b + a in its partner (identical in IEEE arithmetic).
 constexpr int DPP_XOR1 = 0xB1, DPP_XOR2 = 0x4E, DPP_HALF_MIRROR = 0x141, DPP_MIRROR = 0x140;
 
+// DPP row broadcasts (wave64): lane 15 of each row into the whole next row
+// (row 0 has no source), and lane 31 into rows 2 and 3.  Lanes without a
+// source keep an unspecified value; the reductions below never read them.
+constexpr int DPP_BCAST15 = 0x142, DPP_BCAST31 = 0x143;
+
 // Sum over the G lanes of a group (G = 8, 16, 32, 64); every lane of the
-// group receives the bitwise same value.
+// group receives the bitwise same value.  With row sums r0..r3, a 64-lane
+// group gets (r0 + r1) + (r2 + r3) and a 32-lane group r0 + r1 or r2 + r3:
+// row 1 adds row 0's sum and row 3 row 2's, row 3 then adds row 1's, and the
+// totals are read from lanes 31 and 63.
 template <int G>
 __device__ __forceinline__ double gsum(double x) {
     static_assert(G == 8 || G == 16 || G == 32 || G == 64, "group size");
@@ -152,14 +160,13 @@ __device__ __forceinline__ double gsum(double x) {
     x += dpp_f64<DPP_XOR2>(x);
     x += dpp_f64<DPP_HALF_MIRROR>(x);
     if constexpr (G >= 16) x += dpp_f64<DPP_MIRROR>(x);
+    if constexpr (G >= 32) x += dpp_f64<DPP_BCAST15>(x);
     if constexpr (G == 32) {
-        const double r0 = readlane_f64(x, 0), r1 = readlane_f64(x, 16);
-        const double r2 = readlane_f64(x, 32), r3 = readlane_f64(x, 48);
-        x = (__lane_id() < 32) ? r0 + r1 : r2 + r3;
+        const double lo = readlane_f64(x, 31), hi = readlane_f64(x, 63);
+        x = (__lane_id() < 32) ? lo : hi;
     } else if constexpr (G == 64) {
-        const double r0 = readlane_f64(x, 0), r1 = readlane_f64(x, 16);
-        const double r2 = readlane_f64(x, 32), r3 = readlane_f64(x, 48);
-        x = (r0 + r1) + (r2 + r3);
+        x += dpp_f64<DPP_BCAST31>(x);
+        x = readlane_f64(x, 63);
     }
     return x;
 }
@@ -170,6 +177,7 @@ __device__ __forceinline__ void gsum2(double &a, double &b) {
     b = gsum<G>(b);
 }
 
+// Maximum over the group's lanes, combined in the same pattern as gsum.
 template <int G>
 __device__ __forceinline__ double gmax(double x) {
     static_assert(G == 8 || G == 16 || G == 32 || G == 64, "group size");
@@ -177,14 +185,13 @@ __device__ __forceinline__ double gmax(double x) {
     x = fmax(x, dpp_f64<DPP_XOR2>(x));
     x = fmax(x, dpp_f64<DPP_HALF_MIRROR>(x));
     if constexpr (G >= 16) x = fmax(x, dpp_f64<DPP_MIRROR>(x));
+    if constexpr (G >= 32) x = fmax(x, dpp_f64<DPP_BCAST15>(x));
     if constexpr (G == 32) {
-        const double r0 = readlane_f64(x, 0), r1 = readlane_f64(x, 16);
-        const double r2 = readlane_f64(x, 32), r3 = readlane_f64(x, 48);
-        x = (__lane_id() < 32) ? fmax(r0, r1) : fmax(r2, r3);
+        const double lo = readlane_f64(x, 31), hi = readlane_f64(x, 63);
+        x = (__lane_id() < 32) ? lo : hi;
     } else if constexpr (G == 64) {
-        const double r0 = readlane_f64(x, 0), r1 = readlane_f64(x, 16);
-        const double r2 = readlane_f64(x, 32), r3 = readlane_f64(x, 48);
-        x = fmax(fmax(r0, r1), fmax(r2, r3));
+        x = fmax(x, dpp_f64<DPP_BCAST31>(x));
+        x = readlane_f64(x, 63);
     }
     return x;
 }
@@ -240,9 +247,14 @@ __device__ __forceinline__ double unpack_c(const double *C, uint32_t id, int s) 
 // (exp(r) - 1 - r)/r^2 on the reduced interval (relative error below 1.6e-17;
 // fit_exp_poly.py prints the coefficients), by Horner, scaled by 2^n.
 // Underflows to exactly 0 below about -745; NaN propagates.  Within about one
-// ulp; written so every Horner step is one FMA.
+// ulp; written so every Horner step is one FMA.  n is rounded by adding
+// 1.5 * 2^52 inside the FMA that forms x/ln2: the sum's unit in the last
+// place is 1, so its low 32 bits are n in two's complement (|n| < 2^31) and
+// serve as the exponent of the final scaling without a conversion.
 __device__ __forceinline__ double exp_cw(double x) {
-    const double n = __builtin_rint(x * 0x1.71547652b82fep+0);
+    constexpr double SHIFT = 0x1.8p52;
+    const double t = __builtin_fma(x, 0x1.71547652b82fep+0, SHIFT);
+    const double n = t - SHIFT;
     const double r = __builtin_fma(-n, 0x1.abc9e3b39803fp-56,
                                    __builtin_fma(-n, 0x1.62e42fefa39efp-1, x));
     double q = 2.5100375832561234e-08;
@@ -257,7 +269,7 @@ __device__ __forceinline__ double exp_cw(double x) {
     q = __builtin_fma(q, r, 0.5000000000000001);
     q = __builtin_fma(q, r, 1.0);
     q = __builtin_fma(q, r, 1.0);
-    return __builtin_ldexp(q, (int)n);
+    return __builtin_ldexp(q, (int)(uint32_t)__double_as_longlong(t));
 }
 
 // Natural logarithm of a positive finite double (NaN otherwise).  With
