@@ -5,15 +5,17 @@
 //   - state element k of y = {T, Y_1..Y_nS} lives on lane k % G, slot k / G;
 //   - reaction unit p (a forward/reverse pair, or one unpaired reaction) is
 //     evaluated by lane p % G, round p / G;
-//   - the net production sum (E:spec-rate) is a load-balanced gather: each
-//     species' nonzero terms, split by the sign of nu'' - nu', are cut into
-//     chunks of at most SEGL terms; chunk c goes to lane c % G, segment c / G,
-//     and every lane runs the same NSEG segments of SEGL terms (short chunks
-//     padded with a zero term), so the loop has no divergence and a
-//     segment's loads issue back to back.  A term is the 16-bit byte offset
-//     of a unit's net rate q (|nu''-nu'| = 2 or 3 repeats the term).  Each
-//     segment's sum is a "piece"; a species adds its positive pieces and
-//     subtracts its negative ones, both consecutive;
+//   - the net production sum (E:spec-rate) is a load-balanced gather in two
+//     levels of fixed shape: each species' nonzero terms, split by the sign
+//     of nu'' - nu', are cut into chunks of at most SEGL terms; chunk c goes
+//     to lane c % G, segment c / G, and every lane runs the same NSEG
+//     segments of SEGL terms (short chunks padded with a zero term), so the
+//     loop has no divergence and a segment's loads issue back to back.  A
+//     term is the 16-bit byte offset of a unit's net rate q (|nu''-nu'| = 2
+//     or 3 repeats the term).  Each segment's sum is a "piece"; then the lane
+//     of state index k adds the L2P positive and subtracts the L2N negative
+//     pieces of species k (16-bit offsets into the piece array, padded with
+//     its zero slot), again the same count in every lane;
 //   - norms and mixture sums are reductions over the G lanes by DPP exchanges
 //     inside 16-lane rows and lane reads across rows, so every lane of a group
 //     holds bitwise identical scalars and takes the same decisions.
@@ -76,8 +78,8 @@ struct Tables {
     const double *eff;       // [NMS][NK] third-body efficiencies by state index
     const double *spec;      // [NFIELD][NK]
     const uint32_t *gather;  // [NSEG * SEGL / 2][G]: two 16-bit terms per word
-    const int32_t *ps;       // [2 NK + 1]: pieces of state index k are
-                             // [ps[2k], ps[2k+1]) positive, [ps[2k+1], ps[2k+2]) negative
+    const uint32_t *gather2; // [NSL * (L2P + L2N) / 2][G]: pieces of state index
+                             // k = s G + g, positive then negative, two per word
 };
 
 // A gather term is the byte offset, inside the group's rate array, of a unit's
@@ -85,7 +87,7 @@ struct Tables {
 constexpr uint32_t TERM_MAX_BYTES = 0xffffu;
 
 struct Params {
-    int nS, N, NK, nU, RU, NSEG, SEGL;
+    int nS, N, NK, nU, RU, NSEG, SEGL, L2P, L2N;
     int RUp, NPR, NMS;               // first round with pressure-dependent units, their
                                      // rounds (RUp + NPR = RU), efficiency sets
     Tables tab;
@@ -227,14 +229,14 @@ struct UnitRegs<0> {};
 struct GroupLds {
     const double *spec;
     const uint32_t *gather;
-    const int32_t *ps;
+    const uint32_t *gather2;
     const double *units;   // LDS copy (RUC == 0 only)
     const double *pdep;    // pressure-dependent records of rounds RUp.. (LDS)
     const double *eff;     // [NMS][NK] efficiency sets (LDS)
     double *Mv;            // [NMS] third-body concentrations of the sets
     double *C;             // [NK] concentrations, C[nS] == 1.0
     double *Q;             // [RU G + 2]: net rates q, then a zero slot
-    double *piece;         // [NSEG * G] partial sums of the gather
+    double *piece;         // [NSEG * G + 2]: partial sums of the gather, then a zero slot
 };
 
 __device__ __forceinline__ double unpack_c(const double *C, uint32_t id, int s) {
@@ -371,13 +373,68 @@ __device__ __forceinline__ void gather_segments(const uint32_t *tw, const unsign
     }
 }
 
+// Sum of N2 (even) terms of one lane: 16-bit byte offsets into base, two per
+// word at tw[e * G]; all loads are issued before the adds (in term order).
+template <int G, int N2>
+__device__ __forceinline__ double sum_terms(const uint32_t *tw, const unsigned char *base) {
+    constexpr int H = N2 / 2;
+    uint32_t w[H];
+#pragma unroll
+    for (int e = 0; e < H; ++e) w[e] = tw[e * G];
+    double v[N2];
+#pragma unroll
+    for (int e = 0; e < H; ++e) {
+        v[2 * e] = *reinterpret_cast<const double *>(base + (w[e] & 0xffffu));
+        v[2 * e + 1] = *reinterpret_cast<const double *>(base + (w[e] >> 16));
+    }
+    double acc = v[0];
+#pragma unroll
+    for (int e = 1; e < N2; ++e) acc += v[e];
+    return acc;
+}
+
+// Second gather level: the net production of each of the lane's state slots,
+// its LP positive pieces minus its LN negative ones.
+template <int G, int NSL, int LP, int LN>
+__device__ __forceinline__ void piece_sums(const uint32_t *tw2, const unsigned char *Pb,
+                                           double (&w)[NSL]) {
+#pragma unroll
+    for (int s = 0; s < NSL; ++s) {
+        const uint32_t *t = tw2 + (size_t)s * ((LP + LN) / 2) * G;
+        w[s] = sum_terms<G, LP>(t, Pb) - sum_terms<G, LN>(t + (LP / 2) * G, Pb);
+    }
+}
+
+// The same for piece counts without an unrolled instance.
+template <int G, int NSL>
+__device__ __forceinline__ void piece_sums_any(const uint32_t *tw2, const unsigned char *Pb,
+                                               int LP, int LN, double (&w)[NSL]) {
+    const int H = (LP + LN) / 2;
+#pragma unroll
+    for (int s = 0; s < NSL; ++s) {
+        const uint32_t *t = tw2 + (size_t)s * H * G;
+        double wp = 0.0, wn = 0.0;
+        for (int e = 0; e < LP / 2; ++e) {
+            const uint32_t x = t[e * G];
+            wp += *reinterpret_cast<const double *>(Pb + (x & 0xffffu));
+            wp += *reinterpret_cast<const double *>(Pb + (x >> 16));
+        }
+        for (int e = LP / 2; e < H; ++e) {
+            const uint32_t x = t[e * G];
+            wn += *reinterpret_cast<const double *>(Pb + (x & 0xffffu));
+            wn += *reinterpret_cast<const double *>(Pb + (x >> 16));
+        }
+        w[s] = wp - wn;
+    }
+}
+
 // Source term of E:mass and E:energy for the group's cell at state z.
 // z/fz hold this lane's NSL elements (index k = s * G + g).
 template <int G, int NSL, int RUC, bool PD>
 __device__ __forceinline__ void rhs_eval(const double (&z)[NSL], double P10, double invP10,
                                          double (&fz)[NSL], const GroupLds &L,
                                          const UnitRegs<RUC> &ur, int g, int N, int RU, int NSEG,
-                                         int SEGL, int RUp, int NMS) {
+                                         int SEGL, int L2P, int L2N, int RUp, int NMS) {
     constexpr int NK = NSL * G;
     const uint32_t oz = opaque_zero();
     const int go = g + (int)oz;
@@ -548,17 +605,27 @@ __device__ __forceinline__ void rhs_eval(const double (&z)[NSL], double P10, dou
         }
     }
     wave_sync();
+    double w[NSL];
+    {
+        const unsigned char *Pb = reinterpret_cast<const unsigned char *>(piece);
+        const uint32_t *tw2 = L.gather2 + go;
+        switch (L2P * 16 + L2N) {   // uniform; the common piece counts are unrolled
+#define RKC_PIECES(LP, LN) \
+        case LP * 16 + LN: piece_sums<G, NSL, LP, LN>(tw2, Pb, w); break;
+        RKC_PIECES(2, 2) RKC_PIECES(2, 4) RKC_PIECES(2, 6) RKC_PIECES(2, 8)
+        RKC_PIECES(4, 2) RKC_PIECES(4, 4) RKC_PIECES(4, 6) RKC_PIECES(4, 8)
+        RKC_PIECES(6, 2) RKC_PIECES(6, 4) RKC_PIECES(6, 6) RKC_PIECES(6, 8)
+        RKC_PIECES(8, 2) RKC_PIECES(8, 4) RKC_PIECES(8, 6) RKC_PIECES(8, 8)
+#undef RKC_PIECES
+        default: piece_sums_any<G, NSL>(tw2, Pb, L2P, L2N, w);
+        }
+    }
     double hs = 0.0;
 #pragma unroll
     for (int s = 0; s < NSL; ++s) {
         const int k = s * G + go;
-        const int q0 = L.ps[2 * k], q1 = L.ps[2 * k + 1], q2 = L.ps[2 * k + 2];
-        double wp = 0.0, wn = 0.0;
-        for (int q = q0; q < q1; ++q) wp += piece[q];
-        for (int q = q1; q < q2; ++q) wn += piece[q];
-        const double w = wp - wn;
-        fz[s] = L.spec[F_W * NK + k] * w * inv_rho;
-        hs += hRT[s] * w;
+        fz[s] = L.spec[F_W * NK + k] * w[s] * inv_rho;
+        hs += hRT[s] * w[s];
     }
     hs = gsum<G>(hs);
     // dT/dt = -sum_i H_i omega_i / (rho cp); R cancels between H and cp.
@@ -594,19 +661,20 @@ constexpr int STATE_BYTES = 320;
 
 // Sizes that fix the LDS layout of a workgroup.
 struct Shape {
-    int NK, RU, G, NSEG, SEGL, NPR, NMS;
+    int NK, RU, G, NSEG, SEGL, L2, NPR, NMS;   // L2 = L2P + L2N
     bool units_in_lds;
 };
 
 __device__ __forceinline__ Shape shape_of(const Params &p, int G, bool units_in_lds) {
-    return Shape{p.NK, p.RU, G, p.NSEG, p.SEGL, p.NPR, p.NMS, units_in_lds};
+    return Shape{p.NK, p.RU, G, p.NSEG, p.SEGL, p.L2P + p.L2N, p.NPR, p.NMS, units_in_lds};
 }
 
 // Doubles of per-group LDS: concentrations, net rates (+ zero slot, padded to
-// even), gather pieces, third-body concentrations of the efficiency sets
-// (padded to even).
+// even), gather pieces (+ zero slot, padded to even), third-body
+// concentrations of the efficiency sets (padded to even).
 __host__ __device__ inline size_t group_doubles(const Shape &s) {
-    return (size_t)s.NK + (size_t)s.RU * s.G + 2 + (size_t)s.NSEG * s.G + (size_t)((s.NMS + 1) & ~1);
+    return (size_t)s.NK + (size_t)s.RU * s.G + 2 + (size_t)s.NSEG * s.G + 2 +
+           (size_t)((s.NMS + 1) & ~1);
 }
 
 // Bytes of dynamic LDS for a workgroup of `groups` groups.
@@ -617,14 +685,13 @@ __host__ __device__ inline size_t lds_bytes(const Shape &s, int groups) {
     b += (size_t)s.NMS * s.NK * 8;
     b += (size_t)groups * group_doubles(s) * 8;
     b += (size_t)groups * STATE_BYTES;
-    b += (size_t)s.NSEG * (s.SEGL / 2) * s.G * 4 + ((size_t)2 * s.NK + 1) * 4;
+    b += (size_t)s.NSEG * (s.SEGL / 2) * s.G * 4 + (size_t)s.NK * (s.L2 / 2) * 4;
     return b;
 }
 
 struct LdsPtrs {
     double *spec, *units, *pdep, *eff;
-    uint32_t *gather;
-    int32_t *ps;
+    uint32_t *gather, *gather2;
     double *groups;
     unsigned char *states;
 };
@@ -642,7 +709,7 @@ __device__ __forceinline__ LdsPtrs carve(unsigned char *base, const Shape &s, in
     l.states = base + off;
     off += (size_t)groups * STATE_BYTES;
     l.gather = reinterpret_cast<uint32_t *>(base + off); off += (size_t)s.NSEG * (s.SEGL / 2) * s.G * 4;
-    l.ps = reinterpret_cast<int32_t *>(base + off);
+    l.gather2 = reinterpret_cast<uint32_t *>(base + off);
     return l;
 }
 
@@ -650,14 +717,14 @@ __device__ __forceinline__ LdsPtrs carve(unsigned char *base, const Shape &s, in
 // concentration 1.0, the zero slot of the signed rates).
 __device__ __forceinline__ GroupLds group_view(const LdsPtrs &lp, const Shape &s, int gib) {
     GroupLds L;
-    L.spec = lp.spec; L.gather = lp.gather; L.ps = lp.ps;
+    L.spec = lp.spec; L.gather = lp.gather; L.gather2 = lp.gather2;
     L.units = lp.units;
     L.pdep = lp.pdep;
     L.eff = lp.eff;
     L.C = lp.groups + (size_t)gib * group_doubles(s);
     L.Q = L.C + s.NK;
     L.piece = L.Q + s.RU * s.G + 2;
-    L.Mv = L.piece + s.NSEG * s.G;
+    L.Mv = L.piece + s.NSEG * s.G + 2;
     return L;
 }
 
@@ -665,14 +732,13 @@ __device__ __forceinline__ void stage_tables(const Params &p, int G, const LdsPt
                                              int n_units_l) {
     double *spec_l = lp.spec, *units_l = lp.units;
     uint32_t *gather_l = lp.gather;
-    int32_t *ps_l = lp.ps;
     const int tid = threadIdx.x, nt = blockDim.x;
     // pressure-dependent records (already interleaved) and efficiency sets
     for (int i = tid; i < p.NPR * G * PDEP_DOUBLES; i += nt) lp.pdep[i] = p.tab.pdep[i];
     for (int i = tid; i < p.NMS * p.NK; i += nt) lp.eff[i] = p.tab.eff[i];
     for (int i = tid; i < NFIELD * p.NK; i += nt) spec_l[i] = p.tab.spec[i];
     for (int i = tid; i < p.NSEG * (p.SEGL / 2) * G; i += nt) gather_l[i] = p.tab.gather[i];
-    for (int i = tid; i <= 2 * p.NK; i += nt) ps_l[i] = p.tab.ps[i];
+    for (int i = tid; i < p.NK * ((p.L2P + p.L2N) / 2); i += nt) lp.gather2[i] = p.tab.gather2[i];
     // unit records, lane-interleaved in 16-byte pieces (see rhs_eval)
     const double2 *ug = reinterpret_cast<const double2 *>(p.tab.units);
     double2 *ul = reinterpret_cast<double2 *>(units_l);
@@ -684,7 +750,10 @@ __device__ __forceinline__ void stage_tables(const Params &p, int G, const LdsPt
 
 __device__ __forceinline__ void group_init(const GroupLds &L, const Params &p, int G, int g) {
     for (int k = g; k < p.NK; k += G) L.C[k] = (k == p.nS) ? 1.0 : 0.0;
-    if (g == 0) { L.Q[p.RU * G] = 0.0; L.Q[p.RU * G + 1] = 0.0; }
+    if (g == 0) {
+        L.Q[p.RU * G] = 0.0; L.Q[p.RU * G + 1] = 0.0;
+        L.piece[p.NSEG * G] = 0.0; L.piece[p.NSEG * G + 1] = 0.0;
+    }
 }
 
 // ------------------------------------------------------- source-term kernel
@@ -729,8 +798,8 @@ __global__ __launch_bounds__((Occ<RUC, NSL>::threads), (Occ<RUC, NSL>::waves)) v
     }
     if (!active) z[0] = (g == 0) ? 1000.0 : z[0];
     const double P10 = active ? p.P[cell] * 10.0 : 1e6;
-    rhs_eval<G, NSL, RUC, PD>(z, P10, 1.0 / P10, fz, L, ur, g, p.N, p.RU, p.NSEG, p.SEGL, p.RUp,
-                              p.NMS);
+    rhs_eval<G, NSL, RUC, PD>(z, P10, 1.0 / P10, fz, L, ur, g, p.N, p.RU, p.NSEG, p.SEGL, p.L2P,
+                              p.L2N, p.RUp, p.NMS);
     if (active) {
 #pragma unroll
         for (int s = 0; s < NSL; ++s) {

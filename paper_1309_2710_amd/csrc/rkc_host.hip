@@ -23,11 +23,11 @@ constexpr double LNA_ZERO = -1e4;          // ln A of a reaction whose rate is i
 // Device tables that depend on the lane-group shape: the species table is
 // laid out with stride NK, the gather is balanced over G lanes.
 struct NkTables {
-    int G = 0, NK = 0, RU = 0, NSEG = 0, SEGL = 0;
+    int G = 0, NK = 0, RU = 0, NSEG = 0, SEGL = 0, L2P = 0, L2N = 0;
     int RUp = 0, NPR = 0, NMS = 0;   // pressure-dependent rounds and efficiency sets
     double *spec = nullptr;
     uint32_t *gather = nullptr;
-    int32_t *ps = nullptr;
+    uint32_t *gather2 = nullptr;
     double *pdep = nullptr;          // [NPR * G][12], lane-interleaved
     double *eff = nullptr;           // [NMS][NK]
 };
@@ -142,15 +142,20 @@ bool hip_failed(hipError_t e, const char *what, int line) {
         if (hip_failed((expr), #expr, __LINE__)) return RKC_EDEVICE;    \
     } while (0)
 
-// Balanced gather for the net production sum (E:spec-rate).  Each species'
-// terms (byte offsets of the units' net rates q, repeated |nu'' - nu'| times),
-// split into positive and negative coefficients, are cut into chunks of at
-// most SEGL terms; chunk c (species-major, positive before negative) runs in
-// lane c % G, segment c / G.  SEGL and NSEG minimise NSEG * (SEGL + 2).
+// Balanced gather for the net production sum (E:spec-rate), in two levels.
+// Level 1: each species' terms (byte offsets of the units' net rates q,
+// repeated |nu'' - nu'| times), split into positive and negative coefficients,
+// are cut into chunks of at most SEGL terms; chunk c (species-major, positive
+// before negative) runs in lane c % G, segment c / G, and its sum is piece c.
+// Level 2: the lane that owns state index k adds the pieces of species k,
+// L2P positive slots and L2N negative ones (byte offsets into the piece array,
+// padded with its zero slot), and takes the difference.  Both levels have the
+// same shape in every lane.  SEGL is chosen to minimise the vector
+// instructions of both levels, about NSEG (2 SEGL + 1) + NSL (2 (L2P + L2N) + 1).
 struct GatherPlan {
-    int NSEG = 1, SEGL = 2;
-    std::vector<uint32_t> words;   // [NSEG * SEGL / 2][G]
-    std::vector<int32_t> ps;       // [2 NK + 1]
+    int NSEG = 1, SEGL = 2, L2P = 2, L2N = 2;
+    std::vector<uint32_t> words;    // [NSEG * SEGL / 2][G]
+    std::vector<uint32_t> words2;   // [NSL * (L2P + L2N) / 2][G]
 };
 
 // Order the terms inside each chunk so that at every position the lanes of a
@@ -194,6 +199,7 @@ int plan_gather(const rkc_mech *m, int G, int NK, int RU, GatherPlan *gp) {
     const int RUG = RU * G;
     if ((size_t)(RUG + 1) * 8 > rkcdev::TERM_MAX_BYTES) return RKC_ENOTSUP;
     const uint32_t zero_term = (uint32_t)(RUG * 8);
+    const int NSL = NK / G;
     // lists[2 i] positive terms of species i, lists[2 i + 1] negative terms
     std::vector<std::vector<uint32_t>> lists(2 * (size_t)m->nS);
     int max_row = 0;
@@ -205,32 +211,51 @@ int plan_gather(const rkc_mech *m, int G, int NK, int RU, GatherPlan *gp) {
         }
         max_row = std::max(max_row, (int)std::max(lists[2 * i].size(), lists[2 * i + 1].size()));
     }
+    auto even = [](long v) { return std::max(2L, v + (v & 1)); };
     long best = -1;
     for (int L = 2; L <= std::max(2, max_row + (max_row & 1)); L += 2) {
-        long chunks = 0;
-        for (const auto &t : lists) chunks += ((long)t.size() + L - 1) / L;
+        long chunks = 0, pp = 0, pn = 0;
+        for (int i = 0; i < m->nS; ++i) {
+            const long a = ((long)lists[2 * i].size() + L - 1) / L;
+            const long b = ((long)lists[2 * i + 1].size() + L - 1) / L;
+            chunks += a + b;
+            pp = std::max(pp, a);
+            pn = std::max(pn, b);
+        }
         const long nseg = std::max(1L, (chunks + G - 1) / G);
-        const long cost = nseg * (L + 2);
-        if (best < 0 || cost < best) { best = cost; gp->SEGL = L; gp->NSEG = (int)nseg; }
+        if ((nseg * G + 1) * 8 > (long)rkcdev::TERM_MAX_BYTES) continue;
+        const long cost = nseg * (2L * L + 1) + (long)NSL * (2 * (even(pp) + even(pn)) + 1);
+        if (best < 0 || cost < best) {
+            best = cost;
+            gp->SEGL = L;
+            gp->NSEG = (int)nseg;
+            gp->L2P = (int)even(pp);
+            gp->L2N = (int)even(pn);
+        }
     }
+    if (best < 0) return RKC_ENOTSUP;
     const int L = gp->SEGL;
     const int half = L / 2;
-    gp->ps.assign(2 * (size_t)NK + 1, 0);
+    const uint32_t zero_piece = (uint32_t)(gp->NSEG * G * 8);
+    const int H2 = (gp->L2P + gp->L2N) / 2;
+    // level-2 slots of state index k: [0, L2P) positive pieces, then negative
+    std::vector<uint32_t> slot((size_t)NK * 2 * H2, zero_piece);
     // terms of chunk (segment sg, lane g) at cell[(sg G + g) L + e], zero-padded
     std::vector<uint32_t> cell((size_t)gp->NSEG * G * L, zero_term);
     int c = 0;
-    for (int k = 0; k < NK; ++k) {
+    for (int k = 1; k <= m->nS; ++k) {
         for (int sign = 0; sign < 2; ++sign) {
-            gp->ps[2 * k + sign] = c;
-            if (k < 1 || k > m->nS) continue;
             const std::vector<uint32_t> &t = lists[2 * (k - 1) + sign];
-            for (size_t b = 0; b < t.size(); b += L, ++c) {
+            int n = 0;
+            for (size_t b = 0; b < t.size(); b += L, ++c, ++n) {
                 const int g = c % G, sg = c / G;
                 for (int e = 0; e < L && b + e < t.size(); ++e)
                     cell[((size_t)sg * G + g) * L + e] = t[b + e];
+                slot[(size_t)k * 2 * H2 + (sign ? gp->L2P : 0) + n] = (uint32_t)(c * 8);
             }
         }
     }
+    if (c > gp->NSEG * G) return RKC_ENOTSUP;   // cannot happen by construction
     order_for_banks(&cell, gp->NSEG, G, L);
     gp->words.assign((size_t)gp->NSEG * half * G, 0u);
     for (int sg = 0; sg < gp->NSEG; ++sg)
@@ -240,8 +265,13 @@ int plan_gather(const rkc_mech *m, int G, int NK, int RU, GatherPlan *gp) {
                 uint32_t &w = gp->words[(size_t)(sg * half + e / 2) * G + g];
                 w = (e % 2) ? ((w & 0xffffu) | (term << 16)) : ((w & 0xffff0000u) | term);
             }
-    gp->ps[2 * NK] = c;
-    if (c > gp->NSEG * G) return RKC_ENOTSUP;   // cannot happen by construction
+    gp->words2.assign((size_t)NSL * H2 * G, 0u);
+    for (int k = 0; k < NK; ++k) {
+        const int s = k / G, g = k % G;
+        for (int e = 0; e < 2 * H2; e += 2)
+            gp->words2[(size_t)(s * H2 + e / 2) * G + g] =
+                slot[(size_t)k * 2 * H2 + e] | (slot[(size_t)k * 2 * H2 + e + 1] << 16);
+    }
     return RKC_OK;
 }
 
@@ -278,6 +308,8 @@ int ensure_tables(rkc_mech *m, int G, int NK, int RU, NkTables **out) {
     t.RU = RU;
     t.NSEG = gp.NSEG;
     t.SEGL = gp.SEGL;
+    t.L2P = gp.L2P;
+    t.L2N = gp.L2N;
     // rounds from RUp on hold the pressure-dependent units (plain ones first)
     t.NMS = (int)m->effsets.size();
     t.RUp = m->n_pdep > 0 ? m->n_plain / G : RU;
@@ -303,13 +335,13 @@ int ensure_tables(rkc_mech *m, int G, int NK, int RU, NkTables **out) {
     if (!ef.empty()) HIP_OK(hipMemcpy(t.eff, ef.data(), ef.size() * 8, hipMemcpyHostToDevice));
     if (hipMalloc(&t.spec, spec.size() * 8) != hipSuccess) return RKC_ENOMEM;
     if (hipMalloc(&t.gather, gp.words.size() * 4) != hipSuccess ||
-        hipMalloc(&t.ps, gp.ps.size() * 4) != hipSuccess) {
+        hipMalloc(&t.gather2, gp.words2.size() * 4) != hipSuccess) {
         (void)hipFree(t.spec); (void)hipFree(t.gather);
         return RKC_ENOMEM;
     }
     HIP_OK(hipMemcpy(t.spec, spec.data(), spec.size() * 8, hipMemcpyHostToDevice));
     HIP_OK(hipMemcpy(t.gather, gp.words.data(), gp.words.size() * 4, hipMemcpyHostToDevice));
-    HIP_OK(hipMemcpy(t.ps, gp.ps.data(), gp.ps.size() * 4, hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(t.gather2, gp.words2.data(), gp.words2.size() * 4, hipMemcpyHostToDevice));
     m->nk.push_back(t);
     *out = &m->nk.back();
     return RKC_OK;
@@ -380,7 +412,8 @@ int plan_launch(const rkc_mech *m, const Choice &ch, const void *kernel, size_t 
     const int max_threads = ch.v.max_threads;
     int gpb = o.block_groups > 0 ? o.block_groups : std::max(1, max_threads / G);
     if (gpb * G > max_threads) gpb = max_threads / G;
-    const rkcdev::Shape sh{NK, ch.RU, G, nk->NSEG, nk->SEGL, nk->NPR, nk->NMS, ch.v.RUC == 0};
+    const rkcdev::Shape sh{NK, ch.RU, G, nk->NSEG, nk->SEGL, nk->L2P + nk->L2N, nk->NPR, nk->NMS,
+                           ch.v.RUC == 0};
     auto need = [&](int groups) { return rkcdev::lds_bytes(sh, groups); };
     while (gpb > 1 && need(gpb) > m->max_lds) --gpb;
     if (need(gpb) > m->max_lds) return RKC_ENOTSUP;
@@ -421,10 +454,12 @@ void fill_params(const rkc_mech *m, const Choice &ch, const NkTables *nk, rkcdev
     p->RU = ch.RU;
     p->NSEG = nk->NSEG;
     p->SEGL = nk->SEGL;
+    p->L2P = nk->L2P;
+    p->L2N = nk->L2N;
     p->tab.units = m->units_d;
     p->tab.spec = nk->spec;
     p->tab.gather = nk->gather;
-    p->tab.ps = nk->ps;
+    p->tab.gather2 = nk->gather2;
     p->tab.pdep = nk->pdep;
     p->tab.eff = nk->eff;
     p->RUp = nk->RUp;
@@ -595,7 +630,7 @@ int rkc_mech_destroy(rkc_mech *m) {
     for (auto &t : m->nk) {
         (void)hipFree(t.spec);
         (void)hipFree(t.gather);
-        (void)hipFree(t.ps);
+        (void)hipFree(t.gather2);
         if (t.pdep) (void)hipFree(t.pdep);
         if (t.eff) (void)hipFree(t.eff);
     }

@@ -239,7 +239,7 @@ __global__ __launch_bounds__((Occ<RUC, NSL>::threads), (Occ<RUC, NSL>::waves)) v
         if (!__any(S.cell >= 0)) break;   // a wave whose groups hold no cell issues nothing
         ++iters;
         rhs_eval<G, NSL, RUC, PD>(z, S.P10, S.invP10, fz, L, ur, g, N, p.RU, p.NSEG, p.SEGL,
-                                  p.RUp, p.NMS);
+                                  p.L2P, p.L2N, p.RUp, p.NMS);
         if (S.cell >= 0) {
             Counts c = S.c;
             c.n_rhs += 1;
@@ -604,7 +604,7 @@ __global__ __launch_bounds__((Occ<RUC, NSL>::threads), (Occ<RUC, NSL>::waves)) v
         if (!__any(S.cell >= 0)) break;   // a wave whose groups hold no cell issues nothing
         ++iters;
         rhs_eval<G, NSL, RUC, PD>(z, S.P10, S.invP10, fz, L, ur, g, N, p.RU, p.NSEG, p.SEGL,
-                                  p.RUp, p.NMS);
+                                  p.L2P, p.L2N, p.RUp, p.NMS);
         if (S.cell >= 0) {
             Counts c = S.c;
             c.n_rhs += 1;
