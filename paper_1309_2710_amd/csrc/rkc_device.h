@@ -253,25 +253,50 @@ __device__ __forceinline__ double unpack_c(const double *C, uint32_t id, int s) 
 // 1.5 * 2^52 inside the FMA that forms x/ln2: the sum's unit in the last
 // place is 1, so its low 32 bits are n in two's complement (|n| < 2^31) and
 // serve as the exponent of the final scaling without a conversion.
-__device__ __forceinline__ double exp_cw(double x) {
-    constexpr double SHIFT = 0x1.8p52;
-    const double t = __builtin_fma(x, 0x1.71547652b82fep+0, SHIFT);
-    const double n = t - SHIFT;
-    const double r = __builtin_fma(-n, 0x1.abc9e3b39803fp-56,
-                                   __builtin_fma(-n, 0x1.62e42fefa39efp-1, x));
-    double q = 2.5100375832561234e-08;
-    q = __builtin_fma(q, r, 2.7620075879983367e-07);
-    q = __builtin_fma(q, r, 2.7557268480310024e-06);
-    q = __builtin_fma(q, r, 2.4801521322368692e-05);
-    q = __builtin_fma(q, r, 0.00019841269863040545);
-    q = __builtin_fma(q, r, 0.0013888888917196719);
-    q = __builtin_fma(q, r, 0.008333333333330065);
-    q = __builtin_fma(q, r, 0.041666666666624164);
-    q = __builtin_fma(q, r, 0.16666666666666669);
-    q = __builtin_fma(q, r, 0.5000000000000001);
+struct ExpK {
+    double log2e, shift, ln2hi, ln2lo, c[10];
+};
+
+__host__ __device__ constexpr ExpK exp_k() {
+    return ExpK{0x1.71547652b82fep+0, 0x1.8p52, 0x1.62e42fefa39efp-1, 0x1.abc9e3b39803fp-56,
+                {2.5100375832561234e-08, 2.7620075879983367e-07, 2.7557268480310024e-06,
+                 2.4801521322368692e-05, 0.00019841269863040545, 0.0013888888917196719,
+                 0.008333333333330065, 0.041666666666624164, 0.16666666666666669,
+                 0.5000000000000001}};
+}
+
+__device__ __forceinline__ double exp_cw(double x, const ExpK &k) {
+    const double t = __builtin_fma(x, k.log2e, k.shift);
+    const double n = t - k.shift;
+    const double r = __builtin_fma(-n, k.ln2lo, __builtin_fma(-n, k.ln2hi, x));
+    double q = k.c[0];
+#pragma unroll
+    for (int i = 1; i < 10; ++i) q = __builtin_fma(q, r, k.c[i]);
     q = __builtin_fma(q, r, 1.0);
     q = __builtin_fma(q, r, 1.0);
     return __builtin_ldexp(q, (int)(uint32_t)__double_as_longlong(t));
+}
+
+__device__ __forceinline__ double exp_cw(double x) { return exp_cw(x, exp_k()); }
+
+// The same constants as values the compiler cannot see through, so that they
+// are materialised where a source-term evaluation starts (scalar moves) and
+// do not occupy scalar registers across the integrator's bookkeeping.
+__device__ __forceinline__ double opaque_sd(double v) {
+    asm volatile("" : "+s"(v));
+    return v;
+}
+
+__device__ __forceinline__ ExpK exp_k_local() {
+    constexpr ExpK c = exp_k();
+    ExpK k;
+    k.log2e = opaque_sd(c.log2e);
+    k.shift = opaque_sd(c.shift);
+    k.ln2hi = opaque_sd(c.ln2hi);
+    k.ln2lo = opaque_sd(c.ln2lo);
+#pragma unroll
+    for (int i = 0; i < 10; ++i) k.c[i] = opaque_sd(c.c[i]);
+    return k;
 }
 
 // Natural logarithm of a positive finite double (NaN otherwise).  With
@@ -282,17 +307,19 @@ __device__ __forceinline__ double exp_cw(double x) {
 // The error is that of exp_cw (about 1e-16 absolute); ln 2 is split into a
 // head with trailing zero bits and a tail so that e ln2_hi is exact.  No
 // division and no polynomial table beyond the exponential's.
-__device__ __forceinline__ double log_pos(double x) {
+__device__ __forceinline__ double log_pos(double x, const ExpK &k) {
     int e;
     const double m = frexp(x, &e);
     const double l0 = (double)__builtin_amdgcn_logf((float)m) * 0x1.62e42fefa39efp-1;
-    const double d = __builtin_fma(m, exp_cw(-l0), -1.0);
+    const double d = __builtin_fma(m, exp_cw(-l0, k), -1.0);
     const double lm = l0 + d * __builtin_fma(d, __builtin_fma(d, 1.0 / 3.0, -0.5), 1.0);
     const double ln2_hi = 0x1.62e42fee00000p-1, ln2_lo = 0x1.a39ef35793c76p-33;
     const double de = (double)e;
     const double r = __builtin_fma(de, ln2_hi, __builtin_fma(de, ln2_lo, lm));
     return (x > 0.0 && x <= 0x1.fffffffffffffp+1023) ? r : __builtin_nan("");
 }
+
+__device__ __forceinline__ double log_pos(double x) { return log_pos(x, exp_k()); }
 
 // x^(-1/3) for a positive finite x.  With x = m 2^e and e = 3q + t,
 // t in {0, 1, 2}: x^(-1/3) = a^(-1/3) 2^(-q), a = m 2^t in [1/2, 4).  A
@@ -336,14 +363,15 @@ constexpr double LN10 = 2.30258509299404568402;
 // F = 1 (Lindemann) or the Troe factor with log10 F = lFc / (1 + f^2),
 // f = (log10 Pr + c) / (n - 0.14 (log10 Pr + c)), c = -0.4 - 0.67 lFc,
 // n = 0.75 - 1.27 lFc, lFc = log10 F_cent.  Zero if k_inf or k_0 [M] is 0.
-__device__ __forceinline__ double falloff_rate(double kinf, double k0M, double lFc, bool troe) {
+__device__ __forceinline__ double falloff_rate(double kinf, double k0M, double lFc, bool troe,
+                                               const ExpK &K) {
     if (!(kinf > 0.0) || !(k0M > 0.0)) return 0.0;
     const double Pr = k0M / kinf;
     double F = 1.0;
     if (troe) {
-        const double x = log_pos(Pr) * INV_LN10 + (-0.4 - 0.67 * lFc);
+        const double x = log_pos(Pr, K) * INV_LN10 + (-0.4 - 0.67 * lFc);
         const double f = x / ((0.75 - 1.27 * lFc) - 0.14 * x);
-        F = exp_cw(lFc / (1.0 + f * f) * LN10);
+        F = exp_cw(lFc / (1.0 + f * f) * LN10, K);
     }
     return kinf * (Pr / (1.0 + Pr)) * F;
 }
@@ -438,9 +466,10 @@ __device__ __forceinline__ void rhs_eval(const double (&z)[NSL], double P10, dou
     constexpr int NK = NSL * G;
     const uint32_t oz = opaque_zero();
     const int go = g + (int)oz;
+    const ExpK K = exp_k_local();
     const double T = gbcast0<G>(z[0]);
     const double invT = rcp_nr(T);
-    const double lnT = log_pos(T);
+    const double lnT = log_pos(T, K);
 
     double sYW = 0.0, sYcp = 0.0;
     double hRT[NSL], invW[NSL];
@@ -495,8 +524,8 @@ __device__ __forceinline__ void rhs_eval(const double (&z)[NSL], double P10, dou
         double q[RUC];
 #pragma unroll
         for (int r = 0; r < RUC; ++r) {
-            const double kf = exp_cw(ur.lnAf[r] + ur.bf[r] * lnT - ur.tf[r] * invT);
-            const double kr = exp_cw(ur.lnAr[r] + ur.br[r] * lnT - ur.tr[r] * invT);
+            const double kf = exp_cw(ur.lnAf[r] + ur.bf[r] * lnT - ur.tf[r] * invT, K);
+            const double kr = exp_cw(ur.lnAr[r] + ur.br[r] * lnT - ur.tr[r] * invT, K);
             const uint32_t a = ur.idf[r] + oz, b = ur.idr[r] + oz;
             const double of = kf * unpack_c(C, a, 0) * unpack_c(C, a, 1) * unpack_c(C, a, 2);
             const double orv = kr * unpack_c(C, b, 0) * unpack_c(C, b, 1) * unpack_c(C, b, 2);
@@ -528,8 +557,8 @@ __device__ __forceinline__ void rhs_eval(const double (&z)[NSL], double P10, dou
             };
             const double cf = cat(a, 0) * cat(a, 1) * cat(a, 2);
             const double cr = cat(b, 0) * cat(b, 1) * cat(b, 2);
-            const double kf = exp_cw(u0.x + u0.y * lnT - u1.x * invT);
-            const double kr = exp_cw(u1.y + u2.x * lnT - u2.y * invT);
+            const double kf = exp_cw(u0.x + u0.y * lnT - u1.x * invT, K);
+            const double kr = exp_cw(u1.y + u2.x * lnT - u2.y * invT, K);
             Q[p] = kf * cf - kr * cr;
         }
         // rounds with pressure-dependent units: third body and falloff (only
@@ -546,8 +575,8 @@ __device__ __forceinline__ void rhs_eval(const double (&z)[NSL], double P10, dou
             };
             const double cf = cat(a, 0) * cat(a, 1) * cat(a, 2);
             const double cr = cat(b, 0) * cat(b, 1) * cat(b, 2);
-            double kf = exp_cw(u0.x + u0.y * lnT - u1.x * invT);
-            double kr = exp_cw(u1.y + u2.x * lnT - u2.y * invT);
+            double kf = exp_cw(u0.x + u0.y * lnT - u1.x * invT, K);
+            double kr = exp_cw(u1.y + u2.x * lnT - u2.y * invT, K);
             const double2 *pd = reinterpret_cast<const double2 *>(L.pdep) +
                                 (size_t)(6 * (r - RUp)) * G + g;
             const double2 d0 = pd[0];
@@ -560,18 +589,18 @@ __device__ __forceinline__ void rhs_eval(const double (&z)[NSL], double P10, dou
                     kr *= M;
                 } else {
                     const double2 d1 = pd[G], d2 = pd[2 * G], d3 = pd[3 * G];
-                    const double k0f = exp_cw(d0.y + d1.x * lnT - d1.y * invT);
-                    const double k0r = exp_cw(d2.x + d2.y * lnT - d3.x * invT);
+                    const double k0f = exp_cw(d0.y + d1.x * lnT - d1.y * invT, K);
+                    const double k0r = exp_cw(d2.x + d2.y * lnT - d3.x * invT, K);
                     double lFc = 0.0;   // log10 of the Troe centre value (Lindemann: F = 1)
                     if (kind == 3) {
                         const double2 d4 = pd[4 * G], d5 = pd[5 * G];
-                        const double Fc = (1.0 - d4.x) * exp_cw(-T * d4.y) +
-                                          d4.x * exp_cw(-T * d5.x) +
-                                          (d5.y > 0.0 ? exp_cw(-d5.y * invT) : 0.0);
-                        lFc = log_pos(Fc) * INV_LN10;
+                        const double Fc = (1.0 - d4.x) * exp_cw(-T * d4.y, K) +
+                                          d4.x * exp_cw(-T * d5.x, K) +
+                                          (d5.y > 0.0 ? exp_cw(-d5.y * invT, K) : 0.0);
+                        lFc = log_pos(Fc, K) * INV_LN10;
                     }
-                    kf = falloff_rate(kf, k0f * M, lFc, kind == 3);
-                    kr = falloff_rate(kr, k0r * M, lFc, kind == 3);
+                    kf = falloff_rate(kf, k0f * M, lFc, kind == 3, K);
+                    kr = falloff_rate(kr, k0r * M, lFc, kind == 3, K);
                 }
             }
             Q[p] = kf * cf - kr * cr;

@@ -146,8 +146,12 @@ __device__ __forceinline__ double rms_norm(const double (&d)[NSL], const double 
         if (k < N) {
             const double m = fmax(fabs(ya[s]), fabs(yb[s]));
             const double w = atol + rtol * m;
-            // d / w; a zero weight (atol = 0 and y = 0) gives a non-finite norm
-            const double q = w > 0.0 ? d[s] * rcp_nr(w) : d[s] / w;
+            // d / w by a refined reciprocal; tiny weights (only possible with
+            // atol = 0) are scaled by 2^200 first, exactly, so that the
+            // reciprocal stays in range.  A zero weight (atol = 0 and y = 0)
+            // gives a non-finite norm.
+            const double sc = (w < 0x1p-900) ? 0x1p200 : 1.0;
+            const double q = (d[s] * sc) * rcp_nr(w * sc);
             s2 += q * q;
         }
     }
