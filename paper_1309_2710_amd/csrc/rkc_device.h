@@ -321,19 +321,23 @@ __device__ __forceinline__ double log_pos(double x, const ExpK &k) {
 
 __device__ __forceinline__ double log_pos(double x) { return log_pos(x, exp_k()); }
 
-// x^(-1/3) for a positive finite x.  With x = m 2^e and e = 3q + t,
-// t in {0, 1, 2}: x^(-1/3) = a^(-1/3) 2^(-q), a = m 2^t in [1/2, 4).  A
-// single-precision seed of a^(-1/3) (hardware log2 and exp2) is refined by two
-// Newton steps for y^-3 = a, y <- y (4 - a y^3)/3, each squaring the relative
-// error (1e-7 -> 1e-13 -> below rounding).  Within a few ulps.
-__device__ __forceinline__ double rcbrt_pos(double x) {
+// x^(-1/6) for a positive finite x.  With x = m 2^e and e = 6q + t,
+// t in 0..5: x^(-1/6) = a^(-1/6) 2^(-q), a = m 2^t in [1/2, 32).  A
+// single-precision seed of a^(-1/6) (hardware log2 and exp2) is refined by two
+// Newton steps for y^-6 = a, y <- y (7 - a y^6)/6, which take the relative
+// error e to about 3.5 e^2 each (2e-7 -> 2e-13 -> below rounding).  Within a
+// few ulps.
+__device__ __forceinline__ double rsixth_pos(double x) {
     int e;
     const double m = frexp(x, &e);
-    const int q = (e >= 0) ? e / 3 : -((2 - e) / 3);
-    const double a = __builtin_ldexp(m, e - 3 * q);
-    double y = (double)__builtin_amdgcn_exp2f(__builtin_amdgcn_logf((float)a) * (-1.0f / 3.0f));
-    y = y * __builtin_fma(-a, y * y * y, 4.0) * (1.0 / 3.0);
-    y = y * __builtin_fma(-a, y * y * y, 4.0) * (1.0 / 3.0);
+    const int q = (e >= 0) ? e / 6 : -((5 - e) / 6);
+    const double a = __builtin_ldexp(m, e - 6 * q);
+    double y = (double)__builtin_amdgcn_exp2f(__builtin_amdgcn_logf((float)a) * (-1.0f / 6.0f));
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double y3 = y * y * y;
+        y = y * __builtin_fma(-a, y3 * y3, 7.0) * (1.0 / 6.0);
+    }
     return __builtin_ldexp(y, -q);
 }
 

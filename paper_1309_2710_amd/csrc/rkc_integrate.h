@@ -134,11 +134,23 @@ __device__ __forceinline__ void store_counts(const Params &p, int cell, int g, c
     }
 }
 
-// Weighted RMS norm (E:rmsE) over the N state components of the group.
+// The kernel's parameter block (the only kernel argument, at the start of
+// the kernarg segment) through a pointer the compiler cannot see through:
+// fields read through it are loaded with scalar loads where they are used,
+// instead of occupying scalar registers for the whole kernel.
+typedef const __attribute__((address_space(4))) Params ParamsK;
+__device__ __forceinline__ ParamsK *params_k() {
+    ParamsK *k = (ParamsK *)__builtin_amdgcn_kernarg_segment_ptr();
+    asm volatile("" : "+s"(k));
+    return k;
+}
+
+// Square of the weighted RMS norm (E:rmsE) over the N state components of
+// the group (the mean of the squared weighted components).
 template <int G, int NSL>
-__device__ __forceinline__ double rms_norm(const double (&d)[NSL], const double (&ya)[NSL],
-                                           const double (&yb)[NSL], double rtol, double atol,
-                                           int g, int N, double invN) {
+__device__ __forceinline__ double rms_norm2(const double (&d)[NSL], const double (&ya)[NSL],
+                                            const double (&yb)[NSL], double rtol, double atol,
+                                            int g, int N, double invN) {
     double s2 = 0.0;
 #pragma unroll
     for (int s = 0; s < NSL; ++s) {
@@ -156,8 +168,12 @@ __device__ __forceinline__ double rms_norm(const double (&d)[NSL], const double 
         }
     }
     s2 = gsum<G>(s2);
-    return sqrt(s2 * invN);
+    return s2 * invN;
 }
+
+// The correctly rounded square root of m is at most 1 exactly when m is at
+// most the double that follows 1 (sqrt(1 + 2^-52) rounds to 1).
+constexpr double NORM2_ACCEPT = 0x1.0000000000001p0;
 
 #define RKC_KERNEL_PROLOGUE                                                                  \
     extern __shared__ __align__(16) unsigned char lds_raw[];                                 \
@@ -242,9 +258,13 @@ __global__ __launch_bounds__((Occ<RUC, NSL>::threads), (Occ<RUC, NSL>::waves)) v
     for (;;) {
         if (!__any(S.cell >= 0)) break;   // a wave whose groups hold no cell issues nothing
         ++iters;
-        rhs_eval<G, NSL, RUC, PD>(z, S.P10, S.invP10, fz, L, ur, g, N, p.RU, p.NSEG, p.SEGL,
-                                  p.L2P, p.L2N, p.RUp, p.NMS);
+        {
+            ParamsK &pr = *params_k();
+            rhs_eval<G, NSL, RUC, PD>(z, S.P10, S.invP10, fz, L, ur, g, N, pr.RU, pr.NSEG, pr.SEGL,
+                                      pr.L2P, pr.L2N, pr.RUp, pr.NMS);
+        }
         if (S.cell >= 0) {
+            ParamsK &pk = *params_k();
             Counts c = S.c;
             c.n_rhs += 1;
             int act = ACT_NONE, fin = ST_OK;
@@ -253,7 +273,7 @@ __global__ __launch_bounds__((Occ<RUC, NSL>::threads), (Occ<RUC, NSL>::waves)) v
                 // (E:rkcj) with the tabulated coefficients of (s, j)
                 const int j = S.j;
                 const double4 cf =
-                    *reinterpret_cast<const double4 *>(p.coef + 4 * (coef_offset(S.s) + j - 1));
+                    *reinterpret_cast<const double4 *>(pk.coef + 4 * (coef_offset(S.s) + j - 1));
                 const double h = S.h;
                 const double c0 = 1.0 - cf.x - cf.y, ch1 = cf.z * h, ch2 = cf.w * h;
 #pragma unroll
@@ -301,8 +321,10 @@ __global__ __launch_bounds__((Occ<RUC, NSL>::threads), (Occ<RUC, NSL>::waves)) v
 #pragma unroll
                 for (int i = 0; i < NSL; ++i)
                     d[i] = 0.8 * (y[i] - wm1[i]) + 0.4 * h * (f0[i] + fz[i]);
-                const double err = rms_norm<G, NSL>(d, y, wm1, p.rtol, p.atol, g, N, p.invN);
-                if (err <= 1.0) {
+                // err = sqrt(e2) is only compared with 1 and raised to -1/3,
+                // so the square root is not formed
+                const double e2 = rms_norm2<G, NSL>(d, y, wm1, pk.rtol, pk.atol, g, N, pk.invN);
+                if (e2 <= NORM2_ACCEPT) {
                     c.n_steps += 1;
 #pragma unroll
                     for (int i = 0; i < NSL; ++i) { y[i] = wm1[i]; f0[i] = fz[i]; }
@@ -318,10 +340,10 @@ __global__ __launch_bounds__((Occ<RUC, NSL>::threads), (Occ<RUC, NSL>::waves)) v
                         // predictive factor is 0.8 (h/h_prev) r^2 / r_prev; an
                         // err_prev of 0 is kept as r_prev = 0 (factor 0)
                         double fac, r = 0.0;
-                        if (err == 0.0) {
+                        if (e2 == 0.0) {
                             fac = 10.0;
                         } else {
-                            r = rcbrt_pos(err);
+                            r = rsixth_pos(e2);
                             if (!S.predictive) fac = 0.8 * r;
                             else if (S.rprev == 0.0) fac = 0.0;
                             else fac = 0.8 * h * r * r * rcp_nr(S.h_prev * S.rprev);
@@ -336,7 +358,7 @@ __global__ __launch_bounds__((Occ<RUC, NSL>::threads), (Occ<RUC, NSL>::waves)) v
                     }
                 } else {
                     c.n_reject += 1;
-                    double fac = isfinite(err) ? 0.8 * rcbrt_pos(err) : 0.1;
+                    double fac = isfinite(e2) ? 0.8 * rsixth_pos(e2) : 0.1;
                     if (fac < 0.1) fac = 0.1;
                     S.h = h * fac;
                     S.need_sigma = 1;
@@ -399,7 +421,7 @@ __global__ __launch_bounds__((Occ<RUC, NSL>::threads), (Occ<RUC, NSL>::waves)) v
                 double d[NSL];
 #pragma unroll
                 for (int i = 0; i < NSL; ++i) d[i] = ht * (fz[i] - f0[i]);
-                const double e0 = rms_norm<G, NSL>(d, y, y, p.rtol, p.atol, g, N, p.invN);
+                const double e0 = sqrt(rms_norm2<G, NSL>(d, y, y, pk.rtol, pk.atol, g, N, pk.invN));
                 if (!isfinite(e0)) {
                     act = ACT_FINISH;
                     fin = ST_NONFINITE;
@@ -430,7 +452,7 @@ __global__ __launch_bounds__((Occ<RUC, NSL>::threads), (Occ<RUC, NSL>::waves)) v
             }
 
             if (act == ACT_BEGIN_STEP) {
-                if (c.n_steps + c.n_reject >= p.max_steps) { act = ACT_FINISH; fin = ST_MAXSTEPS; }
+                if (c.n_steps + c.n_reject >= pk.max_steps) { act = ACT_FINISH; fin = ST_MAXSTEPS; }
                 else if (S.need_sigma) act = ACT_POWER_STEP;
                 else act = ACT_AFTER_SIGMA;
             }
@@ -467,9 +489,9 @@ __global__ __launch_bounds__((Occ<RUC, NSL>::threads), (Occ<RUC, NSL>::waves)) v
                 if (last) h = t_end - t;
                 const double sq = floor(sqrt(1.0 + 1.54 * h * sigma));
                 int s;
-                if (1.0 + sq > (double)p.s_max) {
-                    s = p.s_max;
-                    h = ((double)(p.s_max - 1) * (double)(p.s_max - 1) - 1.0) / (1.54 * sigma);
+                if (1.0 + sq > (double)pk.s_max) {
+                    s = pk.s_max;
+                    h = ((double)(pk.s_max - 1) * (double)(pk.s_max - 1) - 1.0) / (1.54 * sigma);
                     last = 0;
                 } else {
                     s = 1 + (int)sq;
@@ -477,8 +499,8 @@ __global__ __launch_bounds__((Occ<RUC, NSL>::threads), (Occ<RUC, NSL>::waves)) v
                 c.s_hash = (int)((unsigned)c.s_hash * 31u + (unsigned)s);
                 c.s_max_used = max(c.s_max_used, s);
                 double mu_t1;
-                if (s <= p.coef_smax) {
-                    mu_t1 = p.coef[4 * coef_offset(s)];
+                if (s <= pk.coef_smax) {
+                    mu_t1 = pk.coef[4 * coef_offset(s)];
                     S.tab = 1;
                 } else {
                     // Chebyshev values at w0 = 1 + kappa/s^2 up to degree s, for
