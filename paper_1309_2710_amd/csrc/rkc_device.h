@@ -17,8 +17,8 @@
 //     pieces of species k (16-bit offsets into the piece array, padded with
 //     its zero slot), again the same count in every lane;
 //   - norms and mixture sums are reductions over the G lanes by DPP exchanges
-//     inside 16-lane rows and lane reads across rows, so every lane of a group
-//     holds bitwise identical scalars and takes the same decisions.
+//     inside 16-lane rows and DPP row broadcasts across them, so every lane of
+//     a group holds bitwise identical scalars and takes the same decisions.
 // The integrator is written as a state machine in which every iteration of
 // the main loop performs exactly one source-term evaluation for every group
 // of the wave, whatever phase (power iteration, initial step, Chebyshev stage,
@@ -622,6 +622,8 @@ __device__ __forceinline__ void rhs_eval(const double (&z)[NSL], double P10, dou
         case 4: gather_segments<G, 4>(tw, Qb, piece, NSEG, go); break;
         case 6: gather_segments<G, 6>(tw, Qb, piece, NSEG, go); break;
         case 8: gather_segments<G, 8>(tw, Qb, piece, NSEG, go); break;
+        case 10: gather_segments<G, 10>(tw, Qb, piece, NSEG, go); break;
+        case 12: gather_segments<G, 12>(tw, Qb, piece, NSEG, go); break;
         default: {
             const int half = SEGL >> 1;
             for (int sg = 0; sg < NSEG; ++sg) {

@@ -151,7 +151,9 @@ bool hip_failed(hipError_t e, const char *what, int line) {
 // L2P positive slots and L2N negative ones (byte offsets into the piece array,
 // padded with its zero slot), and takes the difference.  Both levels have the
 // same shape in every lane.  SEGL is chosen to minimise the vector
-// instructions of both levels, about NSEG (2 SEGL + 1) + NSL (2 (L2P + L2N) + 1).
+// instructions of both levels, about NSEG (2 SEGL + 1) + NSL (2 (L2P + L2N) + 1),
+// among the lengths the kernels unroll (SEGL <= 12; piece counts above 8 take
+// a loop and are charged three times as much).
 struct GatherPlan {
     int NSEG = 1, SEGL = 2, L2P = 2, L2N = 2;
     std::vector<uint32_t> words;    // [NSEG * SEGL / 2][G]
@@ -213,7 +215,7 @@ int plan_gather(const rkc_mech *m, int G, int NK, int RU, GatherPlan *gp) {
     }
     auto even = [](long v) { return std::max(2L, v + (v & 1)); };
     long best = -1;
-    for (int L = 2; L <= std::max(2, max_row + (max_row & 1)); L += 2) {
+    for (int L = 2; L <= std::min(12, std::max(2, max_row + (max_row & 1))); L += 2) {
         long chunks = 0, pp = 0, pn = 0;
         for (int i = 0; i < m->nS; ++i) {
             const long a = ((long)lists[2 * i].size() + L - 1) / L;
@@ -224,7 +226,9 @@ int plan_gather(const rkc_mech *m, int G, int NK, int RU, GatherPlan *gp) {
         }
         const long nseg = std::max(1L, (chunks + G - 1) / G);
         if ((nseg * G + 1) * 8 > (long)rkcdev::TERM_MAX_BYTES) continue;
-        const long cost = nseg * (2L * L + 1) + (long)NSL * (2 * (even(pp) + even(pn)) + 1);
+        const long l2 = even(pp) + even(pn);
+        const long cost =
+            nseg * (2L * L + 1) + (long)NSL * (2 * l2 + 1) * (even(pp) > 8 || even(pn) > 8 ? 3 : 1);
         if (best < 0 || cost < best) {
             best = cost;
             gp->SEGL = L;
