@@ -157,15 +157,15 @@ def test_edge_cases(R):
     assert (out["status"] == R.CELL_MAXSTEPS).all() and (co["status"] == O.MAXSTEPS).all()
 
 
-def test_full_size_c3_sampled(R):
-    """53sp/634rx at its full 131072 cells, device-resident, in the launch
-    configuration the benchmark times; the oracle checks a strided sample."""
+def _full_size_sampled(R, cfg, n_sample):
+    """A workload at its full cell count, device-resident, in the launch
+    configuration the benchmark uses; the oracle checks a strided sample."""
     import torch
-    _say("full c3 131072 cells")
-    gm, om = mech(R, "c3")
-    c = synth.CONFIGS["c3"]
-    st = synth.config_states("c3")
+    gm, om = mech(R, cfg)
+    c = synth.CONFIGS[cfg]
+    st = synth.config_states(cfg)
     n = st["T"].shape[0]
+    _say("full", cfg, n, "cells")
     T = torch.from_numpy(st["T"]).cuda()
     P = torch.from_numpy(st["P"]).cuda()
     Y = torch.from_numpy(st["Y"]).cuda()
@@ -176,11 +176,28 @@ def test_full_size_c3_sampled(R):
     _say("stats", out["stats"])
     assert (out["status"].cpu().numpy() == 0).all()
     assert np.abs(Yg.sum(1) - st["Y"].sum(1)).max() <= 1e-12
-    idx = np.arange(0, n, n // 64)[:64]
+    idx = np.arange(0, n, n // n_sample)[:n_sample]
     To, Yo, co = om.integrate(st["T"][idx], st["P"][idx], st["Y"][idx], c["dt"], c["rtol"],
                               c["atol"], threads=THREADS)
-    rep = PT.check(Tg[idx], Yg[idx], cg[idx], To, Yo, co, c["rtol"], c["atol"], max_flips("c3", 64))
+    rep = PT.check(Tg[idx], Yg[idx], cg[idx], To, Yo, co, c["rtol"], c["atol"],
+                   max_flips(cfg, n_sample))
     _say(rep)
+
+
+def test_full_size_c3_sampled(R):
+    """53sp/634rx at its full 131072 cells (the benchmark's workload)."""
+    _full_size_sampled(R, "c3", 64)
+
+
+def test_full_size_c2_sampled(R):
+    """13sp/54rx at its full 262144 cells."""
+    _full_size_sampled(R, "c2", 128)
+
+
+def test_full_size_c4_sampled(R):
+    """111sp/1566rx at its full 65536 cells (64 lanes, two state slots per
+    lane, 10-term gather segments)."""
+    _full_size_sampled(R, "c4", 32)
 
 
 def test_ten_consecutive_steps_c3(R):
