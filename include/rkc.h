@@ -65,10 +65,16 @@ extern "C" {
 #define RKC_SCHED_PERSISTENT  2  /* resident grid; groups pull cells from a device queue */
 
 /* ---- placement of reaction parameters (never changes results) --------- */
-#define RKC_PARAMS_AUTO       0  /* LDS (the measured faster placement) */
+#define RKC_PARAMS_AUTO       0  /* LDS (the measured faster placement), or global
+                                    memory when the tables in LDS would hold the
+                                    workgroup below its occupancy target (large
+                                    mechanisms) and such a variant is compiled */
 #define RKC_PARAMS_REGISTERS  1  /* registers, when a variant for the mechanism's size
                                     is compiled (else LDS) */
 #define RKC_PARAMS_LDS        2
+#define RKC_PARAMS_GLOBAL     3  /* reaction parameters and species table read from
+                                    global memory through the caches; RKC_ENOTSUP
+                                    when no such variant is compiled for the shape */
 
 /* Number of int32 per cell in opts->cell_counters. */
 #define RKC_NCOUNTERS 8

@@ -74,6 +74,9 @@ constexpr int MAX_EFFSETS = 16;
 
 struct Tables {
     const double *units;     // [RU * G][8]
+    const double *units_il;  // [RU + 1][4][G] double2: the same records lane-interleaved
+                             // as in LDS, one zero round after the last (read from
+                             // global memory by the RUC = -1 kernels)
     const double *pdep;      // [NPR * G][12], interleaved by lane (rounds RUp..RU-1)
     const double *eff;       // [NMS][NK] third-body efficiencies by state index
     const double *spec;      // [NFIELD][NK]
@@ -225,12 +228,14 @@ struct UnitRegs {
 };
 template <>
 struct UnitRegs<0> {};
+template <>
+struct UnitRegs<-1> {};
 
 struct GroupLds {
     const double *spec;
     const uint32_t *gather;
     const uint32_t *gather2;
-    const double *units;   // LDS copy (RUC == 0 only)
+    const double *units;   // interleaved records: LDS (RUC == 0) or global (RUC == -1)
     const double *pdep;    // pressure-dependent records of rounds RUp.. (LDS)
     const double *eff;     // [NMS][NK] efficiency sets (LDS)
     double *Mv;            // [NMS] third-body concentrations of the sets
@@ -531,9 +536,11 @@ __device__ __forceinline__ void rhs_eval(const double (&z)[NSL], double P10, dou
             const double kf = exp_cw(ur.lnAf[r] + ur.bf[r] * lnT - ur.tf[r] * invT, K);
             const double kr = exp_cw(ur.lnAr[r] + ur.br[r] * lnT - ur.tr[r] * invT, K);
             const uint32_t a = ur.idf[r] + oz, b = ur.idr[r] + oz;
-            const double of = kf * unpack_c(C, a, 0) * unpack_c(C, a, 1) * unpack_c(C, a, 2);
-            const double orv = kr * unpack_c(C, b, 0) * unpack_c(C, b, 1) * unpack_c(C, b, 2);
-            q[r] = of - orv;
+            // the same operations in the same order as the LDS path below, so
+            // the placement of the parameters never changes a result
+            const double cf = unpack_c(C, a, 0) * unpack_c(C, a, 1) * unpack_c(C, a, 2);
+            const double cr = unpack_c(C, b, 0) * unpack_c(C, b, 1) * unpack_c(C, b, 2);
+            q[r] = kf * cf - kr * cr;
         }
 #pragma unroll
         for (int r = 0; r < RUC; ++r) Q[r * G + go] = q[r];
@@ -697,11 +704,14 @@ constexpr int STATE_BYTES = 320;
 // Sizes that fix the LDS layout of a workgroup.
 struct Shape {
     int NK, RU, G, NSEG, SEGL, L2, NPR, NMS;   // L2 = L2P + L2N
-    bool units_in_lds;
+    bool units_in_lds, spec_in_lds;
 };
 
-__device__ __forceinline__ Shape shape_of(const Params &p, int G, bool units_in_lds) {
-    return Shape{p.NK, p.RU, G, p.NSEG, p.SEGL, p.L2P + p.L2N, p.NPR, p.NMS, units_in_lds};
+// Where a kernel variant keeps the reaction parameters: RUC > 0 registers,
+// RUC = 0 LDS, RUC = -1 global memory (read through the caches, with the
+// species table, so that large mechanisms leave LDS to more lane groups).
+__device__ __forceinline__ Shape shape_of(const Params &p, int G, int RUC) {
+    return Shape{p.NK, p.RU, G, p.NSEG, p.SEGL, p.L2P + p.L2N, p.NPR, p.NMS, RUC == 0, RUC >= 0};
 }
 
 // Doubles of per-group LDS: concentrations, net rates (+ zero slot, padded to
@@ -714,7 +724,7 @@ __host__ __device__ inline size_t group_doubles(const Shape &s) {
 
 // Bytes of dynamic LDS for a workgroup of `groups` groups.
 __host__ __device__ inline size_t lds_bytes(const Shape &s, int groups) {
-    size_t b = (size_t)NFIELD * s.NK * 8;
+    size_t b = s.spec_in_lds ? (size_t)NFIELD * s.NK * 8 : 0;
     if (s.units_in_lds) b += (size_t)s.RU * s.G * UNIT_DOUBLES * 8;
     b += (size_t)s.NPR * s.G * PDEP_DOUBLES * 8;
     b += (size_t)s.NMS * s.NK * 8;
@@ -734,7 +744,8 @@ struct LdsPtrs {
 __device__ __forceinline__ LdsPtrs carve(unsigned char *base, const Shape &s, int groups) {
     LdsPtrs l;
     size_t off = 0;
-    l.spec = reinterpret_cast<double *>(base + off); off += (size_t)NFIELD * s.NK * 8;
+    l.spec = reinterpret_cast<double *>(base + off);
+    if (s.spec_in_lds) off += (size_t)NFIELD * s.NK * 8;
     l.units = reinterpret_cast<double *>(base + off);
     if (s.units_in_lds) off += (size_t)s.RU * s.G * UNIT_DOUBLES * 8;
     l.pdep = reinterpret_cast<double *>(base + off); off += (size_t)s.NPR * s.G * PDEP_DOUBLES * 8;
@@ -764,14 +775,15 @@ __device__ __forceinline__ GroupLds group_view(const LdsPtrs &lp, const Shape &s
 }
 
 __device__ __forceinline__ void stage_tables(const Params &p, int G, const LdsPtrs &lp,
-                                             int n_units_l) {
-    double *spec_l = lp.spec, *units_l = lp.units;
+                                             int n_units_l, bool spec_l) {
+    double *spec_lp = lp.spec, *units_l = lp.units;
     uint32_t *gather_l = lp.gather;
     const int tid = threadIdx.x, nt = blockDim.x;
     // pressure-dependent records (already interleaved) and efficiency sets
     for (int i = tid; i < p.NPR * G * PDEP_DOUBLES; i += nt) lp.pdep[i] = p.tab.pdep[i];
     for (int i = tid; i < p.NMS * p.NK; i += nt) lp.eff[i] = p.tab.eff[i];
-    for (int i = tid; i < NFIELD * p.NK; i += nt) spec_l[i] = p.tab.spec[i];
+    if (spec_l)
+        for (int i = tid; i < NFIELD * p.NK; i += nt) spec_lp[i] = p.tab.spec[i];
     for (int i = tid; i < p.NSEG * (p.SEGL / 2) * G; i += nt) gather_l[i] = p.tab.gather[i];
     for (int i = tid; i < p.NK * ((p.L2P + p.L2N) / 2); i += nt) lp.gather2[i] = p.tab.gather2[i];
     // unit records, lane-interleaved in 16-byte pieces (see rhs_eval)
@@ -781,6 +793,13 @@ __device__ __forceinline__ void stage_tables(const Params &p, int G, const LdsPt
         const int unit = i / (UNIT_DOUBLES / 2), q = i % (UNIT_DOUBLES / 2);
         ul[((unit / G) * (UNIT_DOUBLES / 2) + q) * G + unit % G] = ug[i];
     }
+}
+
+// The RUC = -1 kernels read the species table and the lane-interleaved unit
+// records from global memory.
+__device__ __forceinline__ void global_tables(GroupLds &L, const Params &p) {
+    L.spec = p.tab.spec;
+    L.units = p.tab.units_il;
 }
 
 __device__ __forceinline__ void group_init(const GroupLds &L, const Params &p, int G, int g) {
@@ -809,10 +828,11 @@ __global__ __launch_bounds__((Occ<RUC, NSL>::threads), (Occ<RUC, NSL>::waves)) v
     const int groups = blockDim.x / G;
     const int gib = threadIdx.x / G;
     const int g = threadIdx.x % G;
-    const Shape sh = shape_of(p, G, RUC == 0);
+    const Shape sh = shape_of(p, G, RUC);
     LdsPtrs lp = carve(lds_raw, sh, groups);
-    stage_tables(p, G, lp, RUC == 0 ? p.RU * G : 0);
+    stage_tables(p, G, lp, RUC == 0 ? p.RU * G : 0, RUC >= 0);
     GroupLds L = group_view(lp, sh, gib);
+    if constexpr (RUC < 0) global_tables(L, p);
     group_init(L, p, G, g);
     __syncthreads();
     UnitRegs<RUC> ur;

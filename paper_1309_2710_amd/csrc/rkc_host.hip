@@ -28,6 +28,7 @@ struct NkTables {
     double *spec = nullptr;
     uint32_t *gather = nullptr;
     uint32_t *gather2 = nullptr;
+    double *units_il = nullptr;      // [RU + 1][4][G] double2, for the RUC = -1 kernels
     double *pdep = nullptr;          // [NPR * G][12], lane-interleaved
     double *eff = nullptr;           // [NMS][NK]
 };
@@ -346,6 +347,22 @@ int ensure_tables(rkc_mech *m, int G, int NK, int RU, NkTables **out) {
     HIP_OK(hipMemcpy(t.spec, spec.data(), spec.size() * 8, hipMemcpyHostToDevice));
     HIP_OK(hipMemcpy(t.gather, gp.words.data(), gp.words.size() * 4, hipMemcpyHostToDevice));
     HIP_OK(hipMemcpy(t.gather2, gp.words2.data(), gp.words2.size() * 4, hipMemcpyHostToDevice));
+    {
+        // unit records lane-interleaved in 16-byte pieces (piece q of unit
+        // rG + g at double2 (4r + q)G + g), plus one zero round that the
+        // kernels' one-round-ahead read of the reactant slots may touch
+        std::vector<double> il((size_t)(RU + 1) * G * UNIT_DOUBLES, 0.0);
+        for (int u = 0; u < RU * G && u < m->nU_pad; ++u) {
+            const int r = u / G, g = u % G;
+            for (int q = 0; q < UNIT_DOUBLES / 2; ++q) {
+                const size_t at = ((size_t)(4 * r + q) * G + g) * 2;
+                il[at] = m->units_h[(size_t)u * UNIT_DOUBLES + 2 * q];
+                il[at + 1] = m->units_h[(size_t)u * UNIT_DOUBLES + 2 * q + 1];
+            }
+        }
+        if (hipMalloc(&t.units_il, il.size() * 8) != hipSuccess) return RKC_ENOMEM;
+        HIP_OK(hipMemcpy(t.units_il, il.data(), il.size() * 8, hipMemcpyHostToDevice));
+    }
     m->nk.push_back(t);
     *out = &m->nk.back();
     return RKC_OK;
@@ -355,6 +372,21 @@ struct Choice {
     rkchost::VariantDesc v;
     int RU;
 };
+
+const rkchost::VariantDesc *find_variant(int G, int NSL, int RUC) {
+    int n = 0;
+    const rkchost::VariantDesc *tab = nullptr;
+    switch (G) {
+    case 64: tab = rkchost::variants_g64(&n); break;
+    case 32: tab = rkchost::variants_g32(&n); break;
+    case 16: tab = rkchost::variants_g16(&n); break;
+    case 8: tab = rkchost::variants_g8(&n); break;
+    default: return nullptr;
+    }
+    for (int i = 0; i < n; ++i)
+        if (tab[i].NSL == NSL && tab[i].RUC == RUC) return &tab[i];
+    return nullptr;
+}
 
 int choose_variant(const rkc_mech *m, int lanes, int placement, Choice *out) {
     int G = lanes;
@@ -388,6 +420,33 @@ int choose_variant(const rkc_mech *m, int lanes, int placement, Choice *out) {
     return RKC_OK;
 }
 
+rkcdev::Shape shape_for(const Choice &ch, const NkTables *nk) {
+    return rkcdev::Shape{nk->NK, ch.RU, ch.v.G, nk->NSEG, nk->SEGL, nk->L2P + nk->L2N,
+                         nk->NPR, nk->NMS, ch.v.RUC == 0, ch.v.RUC >= 0};
+}
+
+// choose_variant, the device tables of its shape, and the placement of the
+// reaction parameters: automatic placement keeps them in LDS unless LDS then
+// limits the workgroup below the variant's occupancy target and a variant
+// reading them from global memory exists for the same shape.
+int select_variant(rkc_mech *m, const rkc_opts &o, Choice *ch, NkTables **nk) {
+    int rc = choose_variant(m, o.lanes_per_cell, o.param_placement, ch);
+    if (rc) return rc;
+    rc = ensure_tables(m, ch->v.G, ch->v.NSL * ch->v.G, ch->RU, nk);
+    if (rc) return rc;
+    if (ch->v.RUC != 0 || o.param_placement == RKC_PARAMS_LDS) return RKC_OK;
+    const rkchost::VariantDesc *glob = find_variant(ch->v.G, ch->v.NSL, -1);
+    if (!glob) return o.param_placement == RKC_PARAMS_GLOBAL ? RKC_ENOTSUP : RKC_OK;
+    bool use = o.param_placement == RKC_PARAMS_GLOBAL;
+    if (!use) {
+        const int want = std::max(1, ch->v.max_threads / ch->v.G);
+        const rkcdev::Shape sh = shape_for(*ch, *nk);
+        use = rkcdev::lds_bytes(sh, want) > m->max_lds;
+    }
+    if (use) ch->v = *glob;
+    return RKC_OK;
+}
+
 int ensure_stage(rkc_mech *m, size_t bytes) {
     if (m->stage_bytes >= bytes) return RKC_OK;
     if (m->stage_d) (void)hipFree(m->stage_d);
@@ -416,8 +475,7 @@ int plan_launch(const rkc_mech *m, const Choice &ch, const void *kernel, size_t 
     const int max_threads = ch.v.max_threads;
     int gpb = o.block_groups > 0 ? o.block_groups : std::max(1, max_threads / G);
     if (gpb * G > max_threads) gpb = max_threads / G;
-    const rkcdev::Shape sh{NK, ch.RU, G, nk->NSEG, nk->SEGL, nk->L2P + nk->L2N, nk->NPR, nk->NMS,
-                           ch.v.RUC == 0};
+    const rkcdev::Shape sh = shape_for(ch, nk);
     auto need = [&](int groups) { return rkcdev::lds_bytes(sh, groups); };
     while (gpb > 1 && need(gpb) > m->max_lds) --gpb;
     if (need(gpb) > m->max_lds) return RKC_ENOTSUP;
@@ -464,6 +522,7 @@ void fill_params(const rkc_mech *m, const Choice &ch, const NkTables *nk, rkcdev
     p->tab.spec = nk->spec;
     p->tab.gather = nk->gather;
     p->tab.gather2 = nk->gather2;
+    p->tab.units_il = nk->units_il;
     p->tab.pdep = nk->pdep;
     p->tab.eff = nk->eff;
     p->RUp = nk->RUp;
@@ -505,7 +564,7 @@ int check_integrate_args(double dt, double rtol, double atol, const rkc_opts &o)
     if (o.method != RKC_METHOD_RKC && o.method != RKC_METHOD_RKCK) return RKC_EINVAL;
     if (o.s_max < 2 || o.max_steps < 1) return RKC_EINVAL;
     if (o.schedule < 0 || o.schedule > 2 || o.block_groups < 0 || o.grid_blocks < 0 ||
-        o.param_placement < 0 || o.param_placement > 2)
+        o.param_placement < 0 || o.param_placement > 3)
         return RKC_EINVAL;
     return RKC_OK;
 }
@@ -514,10 +573,8 @@ int enqueue_integrate(rkc_mech *m, size_t n, double *Td, const double *Pd, doubl
                       double rtol, double atol, const rkc_opts &o, int32_t *sd, int32_t *cd,
                       unsigned long long *agg_d, int *queue_d, hipStream_t st, LaunchInfo *li) {
     Choice ch;
-    int rc = choose_variant(m, o.lanes_per_cell, o.param_placement, &ch);
-    if (rc) return rc;
     NkTables *nk = nullptr;
-    rc = ensure_tables(m, ch.v.G, ch.v.NSL * ch.v.G, ch.RU, &nk);
+    int rc = select_variant(m, o, &ch, &nk);
     if (rc) return rc;
     const bool pd = m->n_pdep > 0;
     const void *kernel = o.method == RKC_METHOD_RKC ? (pd ? ch.v.k_rkc_pd : ch.v.k_rkc)
@@ -563,10 +620,8 @@ int enqueue_integrate(rkc_mech *m, size_t n, double *Td, const double *Pd, doubl
 
 int prepare(rkc_mech *m, const rkc_opts &o, size_t n_cells) {
     Choice ch;
-    int rc = choose_variant(m, o.lanes_per_cell, o.param_placement, &ch);
-    if (rc) return rc;
     NkTables *nk = nullptr;
-    rc = ensure_tables(m, ch.v.G, ch.v.NSL * ch.v.G, ch.RU, &nk);
+    int rc = select_variant(m, o, &ch, &nk);
     if (rc || n_cells == 0) return rc;
     // sets the kernels' dynamic-LDS limit now rather than inside a capture
     Launch L;
@@ -635,6 +690,7 @@ int rkc_mech_destroy(rkc_mech *m) {
         (void)hipFree(t.spec);
         (void)hipFree(t.gather);
         (void)hipFree(t.gather2);
+        if (t.units_il) (void)hipFree(t.units_il);
         if (t.pdep) (void)hipFree(t.pdep);
         if (t.eff) (void)hipFree(t.eff);
     }
@@ -875,10 +931,8 @@ int rkc_rhs(const rkc_mech *mc, size_t n, const double *T, const double *P, cons
     HIP_OK(hipGetDevice(&cur));
     if (cur != m->device) HIP_OK(hipSetDevice(m->device));
     Choice ch;
-    int rc = choose_variant(m, o.lanes_per_cell, o.param_placement, &ch);
-    if (rc) return rc;
     NkTables *nk = nullptr;
-    rc = ensure_tables(m, ch.v.G, ch.v.NSL * ch.v.G, ch.RU, &nk);
+    int rc = select_variant(m, o, &ch, &nk);
     if (rc) return rc;
     hipStream_t st = (hipStream_t)o.stream;
     const double *Td = T, *Pd = P, *Yd = Y;

@@ -180,10 +180,11 @@ constexpr double NORM2_ACCEPT = 0x1.0000000000001p0;
     const int groups = blockDim.x / G;                                                       \
     const int gib = threadIdx.x / G;                                                         \
     const int g = threadIdx.x % G;                                                           \
-    const Shape sh = shape_of(p, G, RUC == 0);                                               \
+    const Shape sh = shape_of(p, G, RUC);                                                    \
     LdsPtrs lp = carve(lds_raw, sh, groups);                                                 \
-    stage_tables(p, G, lp, RUC == 0 ? p.RU * G : 0);                                         \
+    stage_tables(p, G, lp, RUC == 0 ? p.RU * G : 0, RUC >= 0);                               \
     GroupLds L = group_view(lp, sh, gib);                                                    \
+    if constexpr (RUC < 0) global_tables(L, p);                                              \
     group_init(L, p, G, g);                                                                  \
     __syncthreads();                                                                         \
     UnitRegs<RUC> ur;                                                                        \

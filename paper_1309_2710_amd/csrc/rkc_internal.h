@@ -10,7 +10,7 @@ namespace rkchost {
 
 // One compiled kernel variant: G lanes per cell, NSL state elements per lane,
 // RUC reaction units per lane held in registers (0: parameters read from LDS,
-// any number of units).
+// -1: from global memory, any number of units).
 struct VariantDesc {
     int G, NSL, RUC;
     int max_threads;
@@ -79,6 +79,19 @@ void fill_stats(const unsigned long long *agg, const LaunchInfo &li, rkc_stats *
     }
 
 // A variant with both kernel sets (parameters in LDS).
+// Plain and pressure-dependent kernels with the reaction parameters and the
+// species table in global memory (RUC = -1).
+#define RKC_VARIANT_PD_GLOBAL(G_, NSL_)                                                        \
+    rkchost::VariantDesc {                                                                     \
+        G_, NSL_, -1, (rkcdev::Occ<0, NSL_>::threads),                                         \
+            reinterpret_cast<const void *>(&rkcdev::rkc_kernel<G_, NSL_, -1, false>),          \
+            reinterpret_cast<const void *>(&rkcdev::rkck_kernel<G_, NSL_, -1, false>),         \
+            reinterpret_cast<const void *>(&rkcdev::rhs_kernel<G_, NSL_, -1, false>),          \
+            reinterpret_cast<const void *>(&rkcdev::rkc_kernel<G_, NSL_, -1, true>),           \
+            reinterpret_cast<const void *>(&rkcdev::rkck_kernel<G_, NSL_, -1, true>),          \
+            reinterpret_cast<const void *>(&rkcdev::rhs_kernel<G_, NSL_, -1, true>)            \
+    }
+
 #define RKC_VARIANT_PD(G_, NSL_)                                                               \
     rkchost::VariantDesc {                                                                     \
         G_, NSL_, 0, (rkcdev::Occ<0, NSL_>::threads),                                          \

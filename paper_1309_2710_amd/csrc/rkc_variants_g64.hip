@@ -4,7 +4,8 @@
 
 namespace rkchost {
 
-static const VariantDesc kTable[] = {RKC_VARIANT(64, 1, 5), RKC_VARIANT_PD(64, 1), RKC_VARIANT_PD(64, 2), RKC_VARIANT_PD(64, 4)};
+static const VariantDesc kTable[] = {RKC_VARIANT(64, 1, 5), RKC_VARIANT_PD(64, 1), RKC_VARIANT_PD(64, 2), RKC_VARIANT_PD(64, 4),
+                                     RKC_VARIANT_PD_GLOBAL(64, 2), RKC_VARIANT_PD_GLOBAL(64, 4)};
 
 const VariantDesc *variants_g64(int *n) {
     *n = (int)(sizeof(kTable) / sizeof(kTable[0]));

@@ -23,7 +23,7 @@ OK, EINVAL, ENOMEM, EDEVICE, ECELLS, ENOTSUP = 0, -1, -2, -3, -4, -5
 CELL_OK, CELL_UNDERFLOW, CELL_MAXSTEPS, CELL_NONFINITE, CELL_BADINPUT = 0, 1, 2, 3, 4
 RKC, RKCK = 0, 1
 SCHED_AUTO, SCHED_PLAIN, SCHED_PERSISTENT = 0, 1, 2
-PARAMS_AUTO, PARAMS_REGISTERS, PARAMS_LDS = 0, 1, 2
+PARAMS_AUTO, PARAMS_REGISTERS, PARAMS_LDS, PARAMS_GLOBAL = 0, 1, 2, 3
 NCOUNTERS = 8
 COUNTER_FIELDS = ["n_rhs", "n_steps", "n_reject", "n_sigma", "s_max_used", "s_hash", "status",
                   "n_power_iter"]

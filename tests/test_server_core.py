@@ -43,7 +43,7 @@ def test_server_rejects_bad_options_without_a_device():
     assert (o.budget_bytes, o.n_streams, o.max_batch_cells) == (1 << 30, 4, 1 << 20)
     h = ct.c_void_p()
     for field, bad in [("n_streams", 0), ("n_streams", 17), ("budget_bytes", 1000),
-                       ("max_batch_cells", 0), ("lanes_per_cell", 12), ("param_placement", 3)]:
+                       ("max_batch_cells", 0), ("lanes_per_cell", 12), ("param_placement", 4)]:
         b = rkc.ServerOpts()
         L.rkc_server_opts_default(ct.byref(b))
         setattr(b, field, bad)
