@@ -422,6 +422,14 @@ CONFIGS = {
                dt=1e-5, rtol=1e-6, atol=1e-10, ea_max=3e5, T_range=(700.0, 2500.0),
                P_max=ATM, s_target=200, limits={"C": 3, "H": 8, "O": 3, "N": 2},
                max_atoms=8, label="111sp/1566rx, 65536 cells, dt 1e-5"),
+    # the 111-species set with third-body and falloff pairs (as c3p)
+    "c4p": dict(n_species=111, n_reactions=1566, elements=["H", "O", "C", "N", "Ar"],
+                mech_seed=1004, pdep_seed=1104, pdep_frac=(0.09, 0.09), state_seed=2004,
+                n_cells=65536, T=("bimodal", 800.0, 2400.0, 20.0), P=("const", ATM),
+                Y=("dirichlet",), dt=1e-5, rtol=1e-6, atol=1e-10, ea_max=3e5,
+                T_range=(700.0, 2500.0), P_max=ATM, s_target=200,
+                limits={"C": 3, "H": 8, "O": 3, "N": 2}, max_atoms=8,
+                label="111sp/1566rx with third-body and falloff pairs, 65536 cells, dt 1e-5"),
 }
 
 

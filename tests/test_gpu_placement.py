@@ -56,6 +56,25 @@ def test_global_tables_equal_lds_and_oracle(R):
     PT.check(Tg, Yg, og["counters"], To, Yo, co, c["rtol"], c["atol"], max(2, int(0.15 * 24)))
 
 
+def test_global_tables_with_falloff(R):
+    """The pressure-dependent kernels of the global-memory placement: the
+    111-species set with third-body and falloff pairs, global against LDS bit
+    for bit and against the oracle."""
+    _say("placement c4p")
+    m = synth.config_mechanism("c4p")
+    gm = R.Mechanism(m)
+    st = synth.config_states("c4p", 12)
+    Tl, Yl, ol = _run(R, gm, "c4p", st, R.PARAMS_LDS)
+    Tg, Yg, og = _run(R, gm, "c4p", st, R.PARAMS_GLOBAL)
+    _say("lds", ol["stats"], "global", og["stats"])
+    assert np.array_equal(Tl, Tg) and np.array_equal(Yl, Yg)
+    assert np.array_equal(ol["counters"], og["counters"])
+    c = synth.CONFIGS["c4p"]
+    To, Yo, co = O.Model(m).integrate(st["T"], st["P"], st["Y"], c["dt"], c["rtol"], c["atol"],
+                                      threads=16)
+    PT.check(Tg, Yg, og["counters"], To, Yo, co, c["rtol"], c["atol"], max(2, int(0.15 * 12)))
+
+
 def test_registers_equal_lds(R):
     _say("placement registers c3")
     m = synth.config_mechanism("c3")
