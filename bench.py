@@ -110,7 +110,7 @@ def main():
     ap.add_argument("--config", default="c3")
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--schedule", type=int, default=0)
-    ap.add_argument("--params", type=int, default=0, help="0 auto, 1 registers, 2 LDS")
+    ap.add_argument("--params", type=int, default=0, help="0 auto, 1 registers, 2 LDS, 3 global memory")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--autotune", action="store_true",
                     help="choose schedule and workgroup size with rkc_autotune on a strided "

@@ -176,10 +176,32 @@ __device__ __forceinline__ double gsum(double x) {
     return x;
 }
 
+// Two sums at once.  For a 64-lane group the upper half of a trades places
+// with the lower half of b (v_permlane32_swap), so that one addition leaves
+// a's half-sums (a_l + a_{l+32}) in lanes 0..31 and b's in lanes 32..63; the
+// row reductions and one row broadcast then serve both, and the totals are
+// read from lanes 31 and 63.  Every lane receives the bitwise same values.
 template <int G>
 __device__ __forceinline__ void gsum2(double &a, double &b) {
-    a = gsum<G>(a);
-    b = gsum<G>(b);
+    if constexpr (G == 64) {
+        const long long va = __double_as_longlong(a), vb = __double_as_longlong(b);
+        const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)va, (unsigned)vb, false, false);
+        const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(va >> 32), (unsigned)(vb >> 32),
+                                                         false, false);
+        const double a2 = __longlong_as_double(((long long)hi[0] << 32) | (unsigned)lo[0]);
+        const double b2 = __longlong_as_double(((long long)hi[1] << 32) | (unsigned)lo[1]);
+        double x = a2 + b2;
+        x += dpp_f64<DPP_XOR1>(x);
+        x += dpp_f64<DPP_XOR2>(x);
+        x += dpp_f64<DPP_HALF_MIRROR>(x);
+        x += dpp_f64<DPP_MIRROR>(x);
+        x += dpp_f64<DPP_BCAST15>(x);
+        a = readlane_f64(x, 31);
+        b = readlane_f64(x, 63);
+    } else {
+        a = gsum<G>(a);
+        b = gsum<G>(b);
+    }
 }
 
 // Maximum over the group's lanes, combined in the same pattern as gsum.
@@ -518,12 +540,23 @@ __device__ __forceinline__ void rhs_eval(const double (&z)[NSL], double P10, dou
     }
     // third-body concentration of each efficiency set, [M] = sum_i alpha_i C_i
     if constexpr (PD)
-    for (int q = 0; q < NMS; ++q) {
-        double part = 0.0;
+    for (int q = 0; q < NMS; q += 2) {
+        double p0 = 0.0, p1 = 0.0;
+        const bool two = q + 1 < NMS;
 #pragma unroll
-        for (int s = 0; s < NSL; ++s) part += L.eff[q * NK + s * G + go] * Ck[s];
-        part = gsum<G>(part);
-        if (g == 0) L.Mv[q] = part;
+        for (int s = 0; s < NSL; ++s) {
+            p0 += L.eff[q * NK + s * G + go] * Ck[s];
+            if (two) p1 += L.eff[(q + 1) * NK + s * G + go] * Ck[s];
+        }
+        if (two) {
+            gsum2<G>(p0, p1);
+        } else {
+            p0 = gsum<G>(p0);
+        }
+        if (g == 0) {
+            L.Mv[q] = p0;
+            if (two) L.Mv[q + 1] = p1;
+        }
     }
     wave_sync();
 

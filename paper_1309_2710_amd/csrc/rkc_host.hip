@@ -129,9 +129,12 @@ std::vector<double> coef_table() {
 }
 
 // A failed HIP call returns RKC_EDEVICE; with RKC_DEBUG set in the
-// environment it is also reported on stderr.
+// environment it is also reported on stderr. The runtime's per-thread last
+// error is cleared, so that a failure reported here is not reported a second
+// time by the caller's own next error check.
 bool hip_failed(hipError_t e, const char *what, int line) {
     if (e == hipSuccess) return false;
+    (void)hipGetLastError();
     if (std::getenv("RKC_DEBUG"))
         std::fprintf(stderr, "rkc: %s failed at rkc_host.hip:%d: %s\n", what, line,
                      hipGetErrorString(e));
@@ -482,6 +485,10 @@ int plan_launch(const rkc_mech *m, const Choice &ch, const void *kernel, size_t 
     L->groups_per_block = gpb;
     L->threads = gpb * G;
     L->lds = need(gpb);
+    // The workgroup must fit the kernel's own launch bound.
+    hipFuncAttributes fa{};
+    HIP_OK(hipFuncGetAttributes(&fa, kernel));
+    if (L->threads > fa.maxThreadsPerBlock) return RKC_ENOTSUP;
     if (hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L->lds) !=
         hipSuccess)
         return RKC_EDEVICE;

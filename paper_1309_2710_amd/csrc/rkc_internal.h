@@ -83,7 +83,7 @@ void fill_stats(const unsigned long long *agg, const LaunchInfo &li, rkc_stats *
 // species table in global memory (RUC = -1).
 #define RKC_VARIANT_PD_GLOBAL(G_, NSL_)                                                        \
     rkchost::VariantDesc {                                                                     \
-        G_, NSL_, -1, (rkcdev::Occ<0, NSL_>::threads),                                         \
+        G_, NSL_, -1, (rkcdev::Occ<-1, NSL_>::threads),                                        \
             reinterpret_cast<const void *>(&rkcdev::rkc_kernel<G_, NSL_, -1, false>),          \
             reinterpret_cast<const void *>(&rkcdev::rkck_kernel<G_, NSL_, -1, false>),         \
             reinterpret_cast<const void *>(&rkcdev::rhs_kernel<G_, NSL_, -1, false>),          \
