@@ -140,7 +140,10 @@ typedef struct {
     int32_t method;          /* RKC_METHOD_RKC */
     int32_t s_max;           /* 1000: largest RKC stage count (>= 2) */
     int32_t max_steps;       /* 1000000: accepted + rejected steps per cell */
-    int32_t lanes_per_cell;  /* 0 = automatic; else 8, 16, 32 or 64 */
+    int32_t lanes_per_cell;  /* 0 = automatic; else 8, 16, 32 or 64.  Automatic:
+                                N = n_species + 1 state elements, 16 lanes for
+                                N <= 16, 32 for N <= 39 (or N <= 64 with
+                                pressure-dependent reactions), else 64 */
     int32_t schedule;        /* RKC_SCHED_AUTO */
     int32_t block_groups;    /* lane groups per workgroup, 0 = automatic */
     int32_t grid_blocks;     /* persistent grid size in workgroups, 0 = automatic */

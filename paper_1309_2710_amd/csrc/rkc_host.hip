@@ -391,9 +391,19 @@ const rkchost::VariantDesc *find_variant(int G, int NSL, int RUC) {
     return nullptr;
 }
 
+// Automatic group size: 16 lanes up to 16 state elements, 32 up to 39, 64
+// above.  A set with pressure-dependent units and at most 64 state elements
+// keeps 32 lanes (two slots per lane, two cells per wave): the work that every
+// lane repeats per cell (group reductions, third-body sums, step control) is
+// then shared by two cells, which outweighs the lower occupancy of the
+// two-slot kernels (53-species falloff set: 3.23 M against 2.79 M cell-ODEs/s
+// at 64 lanes; without pressure-dependent units the two are level).
 int choose_variant(const rkc_mech *m, int lanes, int placement, Choice *out) {
     int G = lanes;
-    if (G == 0) G = (m->N >= 40) ? 64 : (m->N > 16 ? 32 : 16);
+    if (G == 0) {
+        G = (m->N >= 40) ? 64 : (m->N > 16 ? 32 : 16);
+        if (G == 64 && m->n_pdep > 0 && m->N <= 64) G = 32;
+    }
     int n = 0;
     const rkchost::VariantDesc *tab = nullptr;
     switch (G) {
