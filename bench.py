@@ -34,7 +34,7 @@ METRIC = "cell-ODEs integrated per sec over dt (53sp/634rx, FP64); p99 batch lat
 
 
 def rhs_flops(mech):
-    """Algorithmic FP64 flops of one source-term evaluation (see DESIGN.md).
+    """Algorithmic FP64 flops of one source-term evaluation.
 
     Per reaction: exponent argument 4, exp EXP_FLOPS, rate of progress m_j
     multiplies; per forward/reverse pair one subtraction; per nonzero
@@ -135,8 +135,8 @@ def main():
                          "timed region: the known-size reference for HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only; the cells of a global step "
-              "are independent and would shard by contiguous cell ranges (see DESIGN.md)",
+        print("bench.py: measures one GPU only (--gpus 1); the cells of a global step "
+              "are independent and would shard by contiguous cell ranges",
               file=sys.stderr)
         sys.exit(2)
 

@@ -16,7 +16,7 @@
  *     error estimate and weighted RMS norm (E:rmsE), step-size controller,
  *     initial step, stage count, nonlinear power method for the spectral radius.
  *
- * Readings where the paper is silent or garbled (each is listed in the design doc):
+ * Readings where the paper is silent or garbled:
  *   b_1 = 1/omega_0 as printed; a_j = 1 - b_j T_j(omega_0); stage count is
  *   1 + floor(sqrt(1 + 1.54 h sigma)), capped at s_max; predictive controller
  *   0.8 (h_n/h_{n-1}) err_n^{1/3} / err_{n+1}^{2/3}, non-predictive 0.8/err^{1/3}
