@@ -169,6 +169,7 @@ typedef struct {
                                 whether or not the group still holds a cell, so
                                 n_rhs / n_rhs_slots is the fraction of issued work that
                                 advanced a cell (1 = no idle groups) */
+    int32_t param_placement; /* placement that ran: RKC_PARAMS_REGISTERS, _LDS or _GLOBAL */
 } rkc_stats;
 
 /* Fill *opts with the defaults.  Returns RKC_EINVAL for NULL. */

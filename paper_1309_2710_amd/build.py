@@ -19,7 +19,10 @@ LIB = os.path.join(HERE, "librkc.so")
 ARCH = os.environ.get("RKC_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-CFLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
+# -ffp-contract=on: a multiply and an add are fused only inside one source
+# expression, so every kernel variant that shares an expression rounds it the
+# same way (the default also fuses across statements, depending on context).
+CFLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH, "-ffp-contract=on",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I" + os.path.join(ROOT, "include"), "-I" + CSRC, "-Wall",
           "-Wno-unused-variable", "-Wno-unused-function"]

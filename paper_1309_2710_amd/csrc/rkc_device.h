@@ -266,6 +266,19 @@ struct GroupLds {
     double *piece;         // [NSEG * G + 2]: partial sums of the gather, then a zero slot
 };
 
+// ln k = ln A + beta ln T - theta/T (E:rxn-const) and the net rate of a
+// forward/reverse pair, each with its roundings written out as FMAs: left to
+// the compiler, the contraction of a sum of products may differ between
+// kernel variants, and every variant must form the same values.
+__device__ __forceinline__ double arrhenius_arg(double lnA, double beta, double theta, double lnT,
+                                                double invT) {
+    return __builtin_fma(-theta, invT, __builtin_fma(beta, lnT, lnA));
+}
+
+__device__ __forceinline__ double net_rate(double kf, double cf, double kr, double cr) {
+    return __builtin_fma(kf, cf, -(kr * cr));
+}
+
 __device__ __forceinline__ double unpack_c(const double *C, uint32_t id, int s) {
     return C[(id >> (10 * s)) & 1023u];
 }
@@ -566,14 +579,14 @@ __device__ __forceinline__ void rhs_eval(const double (&z)[NSL], double P10, dou
         double q[RUC];
 #pragma unroll
         for (int r = 0; r < RUC; ++r) {
-            const double kf = exp_cw(ur.lnAf[r] + ur.bf[r] * lnT - ur.tf[r] * invT, K);
-            const double kr = exp_cw(ur.lnAr[r] + ur.br[r] * lnT - ur.tr[r] * invT, K);
+            const double kf = exp_cw(arrhenius_arg(ur.lnAf[r], ur.bf[r], ur.tf[r], lnT, invT), K);
+            const double kr = exp_cw(arrhenius_arg(ur.lnAr[r], ur.br[r], ur.tr[r], lnT, invT), K);
             const uint32_t a = ur.idf[r] + oz, b = ur.idr[r] + oz;
             // the same operations in the same order as the LDS path below, so
             // the placement of the parameters never changes a result
             const double cf = unpack_c(C, a, 0) * unpack_c(C, a, 1) * unpack_c(C, a, 2);
             const double cr = unpack_c(C, b, 0) * unpack_c(C, b, 1) * unpack_c(C, b, 2);
-            q[r] = kf * cf - kr * cr;
+            q[r] = net_rate(kf, cf, kr, cr);
         }
 #pragma unroll
         for (int r = 0; r < RUC; ++r) Q[r * G + go] = q[r];
@@ -601,9 +614,9 @@ __device__ __forceinline__ void rhs_eval(const double (&z)[NSL], double P10, dou
             };
             const double cf = cat(a, 0) * cat(a, 1) * cat(a, 2);
             const double cr = cat(b, 0) * cat(b, 1) * cat(b, 2);
-            const double kf = exp_cw(u0.x + u0.y * lnT - u1.x * invT, K);
-            const double kr = exp_cw(u1.y + u2.x * lnT - u2.y * invT, K);
-            Q[p] = kf * cf - kr * cr;
+            const double kf = exp_cw(arrhenius_arg(u0.x, u0.y, u1.x, lnT, invT), K);
+            const double kr = exp_cw(arrhenius_arg(u1.y, u2.x, u2.y, lnT, invT), K);
+            Q[p] = net_rate(kf, cf, kr, cr);
         }
         // rounds with pressure-dependent units: third body and falloff (only
         // in the kernels built for mechanisms that have them)
@@ -619,8 +632,8 @@ __device__ __forceinline__ void rhs_eval(const double (&z)[NSL], double P10, dou
             };
             const double cf = cat(a, 0) * cat(a, 1) * cat(a, 2);
             const double cr = cat(b, 0) * cat(b, 1) * cat(b, 2);
-            double kf = exp_cw(u0.x + u0.y * lnT - u1.x * invT, K);
-            double kr = exp_cw(u1.y + u2.x * lnT - u2.y * invT, K);
+            double kf = exp_cw(arrhenius_arg(u0.x, u0.y, u1.x, lnT, invT), K);
+            double kr = exp_cw(arrhenius_arg(u1.y, u2.x, u2.y, lnT, invT), K);
             const double2 *pd = reinterpret_cast<const double2 *>(L.pdep) +
                                 (size_t)(6 * (r - RUp)) * G + g;
             const double2 d0 = pd[0];
@@ -633,8 +646,8 @@ __device__ __forceinline__ void rhs_eval(const double (&z)[NSL], double P10, dou
                     kr *= M;
                 } else {
                     const double2 d1 = pd[G], d2 = pd[2 * G], d3 = pd[3 * G];
-                    const double k0f = exp_cw(d0.y + d1.x * lnT - d1.y * invT, K);
-                    const double k0r = exp_cw(d2.x + d2.y * lnT - d3.x * invT, K);
+                    const double k0f = exp_cw(arrhenius_arg(d0.y, d1.x, d1.y, lnT, invT), K);
+                    const double k0r = exp_cw(arrhenius_arg(d2.x, d2.y, d3.x, lnT, invT), K);
                     double lFc = 0.0;   // log10 of the Troe centre value (Lindemann: F = 1)
                     if (kind == 3) {
                         const double2 d4 = pd[4 * G], d5 = pd[5 * G];
@@ -647,7 +660,7 @@ __device__ __forceinline__ void rhs_eval(const double (&z)[NSL], double P10, dou
                     kr = falloff_rate(kr, k0r * M, lFc, kind == 3, K);
                 }
             }
-            Q[p] = kf * cf - kr * cr;
+            Q[p] = net_rate(kf, cf, kr, cr);
         }
     }
     wave_sync();

@@ -628,6 +628,7 @@ int enqueue_integrate(rkc_mech *m, size_t n, double *Td, const double *Pd, doubl
     void *args[] = {&p};
     HIP_OK(hipLaunchKernel(kernel, dim3(L.blocks), dim3(L.threads), args, L.lds, st));
     li->G = ch.v.G;
+    li->RUC = ch.v.RUC;
     li->persistent = L.persistent;
     li->blocks = L.blocks;
     li->threads = L.threads;
@@ -669,6 +670,8 @@ void fill_stats(const unsigned long long *agg, const LaunchInfo &li, rkc_stats *
     stats->block_threads = li.threads;
     stats->lds_bytes = (int32_t)li.lds;
     stats->n_rhs_slots = (int64_t)agg[8];
+    stats->param_placement = li.RUC > 0 ? RKC_PARAMS_REGISTERS
+                                        : (li.RUC == 0 ? RKC_PARAMS_LDS : RKC_PARAMS_GLOBAL);
 }
 
 }  // namespace rkchost

@@ -34,7 +34,7 @@ constexpr int AGG_N = 16;
 
 // What one integrator launch ran (for rkc_stats).
 struct LaunchInfo {
-    int G = 0, blocks = 0, threads = 0;
+    int G = 0, RUC = 0, blocks = 0, threads = 0;
     bool persistent = false;
     size_t lds = 0;
 };

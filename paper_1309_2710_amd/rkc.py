@@ -63,7 +63,7 @@ class Stats(ct.Structure):
                 ("worst_status", ct.c_int32), ("lanes_per_cell", ct.c_int32),
                 ("schedule", ct.c_int32), ("grid_blocks", ct.c_int32),
                 ("block_threads", ct.c_int32), ("lds_bytes", ct.c_int32),
-                ("n_rhs_slots", ct.c_int64)]
+                ("n_rhs_slots", ct.c_int64), ("param_placement", ct.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

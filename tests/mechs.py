@@ -1,4 +1,7 @@
-"""Hand-built tiny mechanisms for closed-form pins (dict layout of synth)."""
+"""Hand-built tiny mechanisms for closed-form pins (dict layout of synth), and
+seeded synthetic ones at the kernels' largest state sizes."""
+import functools
+
 import numpy as np
 
 from paper_1309_2710_amd.synth import R_J, ATM
@@ -49,3 +52,22 @@ def nonlinear3(W=(10.0, 20.0, 30.0)):
          np.array([4.5, 2e-4, 0, 0, 0, -6000.0, 0])]
     return tiny(list(W), [([0, 1], [2], 1e12, 0.5, 4e4), ([2], [0, 1], 1e9, 0.0, 8e4)],
                 nasa=n)
+
+
+@functools.lru_cache(maxsize=None)
+def seeded(n_species):
+    """Seeded synthetic mechanisms sized to fill four slots per lane: 255
+    species (64 lanes) and 31 species (8 lanes)."""
+    from paper_1309_2710_amd import synth
+    if n_species == 255:
+        return synth.make_mechanism(255, 600, ["H", "O", "C", "N", "Ar"], 4242,
+                                    limits={"C": 4, "H": 10, "O": 4, "N": 2}, max_atoms=12)
+    assert n_species == 31
+    return synth.make_mechanism(31, 120, ["H", "O", "C", "N"], 3131,
+                                limits={"C": 2, "H": 4, "O": 2, "N": 2}, max_atoms=6)
+
+
+def seeded_states(m, n, seed):
+    from paper_1309_2710_amd import synth
+    return synth.make_states(m, n, seed, T_dist=("uniform", 900.0, 1800.0),
+                             P_dist=("const", ATM), Y_dist=("dirichlet",))

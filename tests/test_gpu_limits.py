@@ -2,13 +2,11 @@
 64 lanes x 4 slots) and 31 species on 8 lanes (N = 32 = 8 x 4) match the
 oracle in the source term and over a global step; one species more than the
 64-lane kernels hold is refused before anything is launched."""
-import functools
-
 import numpy as np
 import pytest
 
 from oracle import oracle as O
-from paper_1309_2710_amd import synth
+from tests import mechs
 from tests import parity as PT
 
 pytestmark = pytest.mark.gpu
@@ -25,18 +23,11 @@ def _say(*a):
     print("[case]", *a, flush=True)
 
 
-@functools.lru_cache(maxsize=None)
-def _mech(n_species):
-    if n_species == 255:
-        return synth.make_mechanism(255, 600, ["H", "O", "C", "N", "Ar"], 4242,
-                                    limits={"C": 4, "H": 10, "O": 4, "N": 2}, max_atoms=12)
-    return synth.make_mechanism(31, 120, ["H", "O", "C", "N"], 3131,
-                                limits={"C": 2, "H": 4, "O": 2, "N": 2}, max_atoms=6)
+_mech = mechs.seeded
 
 
 def _states(m, n, seed):
-    return synth.make_states(m, n, seed, T_dist=("uniform", 900.0, 1800.0),
-                             P_dist=("const", synth.ATM), Y_dist=("dirichlet",))
+    return mechs.seeded_states(m, n, seed)
 
 
 @pytest.mark.parametrize("nS,G", [(255, 64), (31, 8)])
