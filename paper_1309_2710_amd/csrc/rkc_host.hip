@@ -146,6 +146,23 @@ bool hip_failed(hipError_t e, const char *what, int line) {
         if (hip_failed((expr), #expr, __LINE__)) return RKC_EDEVICE;    \
     } while (0)
 
+// Makes a device current for the length of one call and gives the caller's
+// current device back when the call returns, whatever the return path.
+struct DeviceScope {
+    int prev = 0;
+    bool switched = false;
+    hipError_t enter(int dev) {
+        hipError_t e = hipGetDevice(&prev);
+        if (e != hipSuccess || prev == dev) return e;
+        e = hipSetDevice(dev);
+        switched = e == hipSuccess;
+        return e;
+    }
+    ~DeviceScope() {
+        if (switched) (void)hipSetDevice(prev);
+    }
+};
+
 // Balanced gather for the net production sum (E:spec-rate), in two levels.
 // Level 1: each species' terms (byte offsets of the units' net rates q,
 // repeated |nu'' - nu'| times), split into positive and negative coefficients,
@@ -947,9 +964,8 @@ int rkc_rhs(const rkc_mech *mc, size_t n, const double *T, const double *P, cons
     if (n == 0) return RKC_OK;
     if (!T || !P || !Y || !f) return RKC_EINVAL;
     if (n > 0x7fffffff) return RKC_ENOTSUP;
-    int cur = 0;
-    HIP_OK(hipGetDevice(&cur));
-    if (cur != m->device) HIP_OK(hipSetDevice(m->device));
+    DeviceScope dev;
+    HIP_OK(dev.enter(m->device));
     Choice ch;
     NkTables *nk = nullptr;
     int rc = select_variant(m, o, &ch, &nk);
@@ -1006,9 +1022,8 @@ int rkc_integrate(const rkc_mech *mc, size_t n, double *T, const double *P, doub
     if (n == 0) return RKC_OK;
     if (!T || !P || !Y) return RKC_EINVAL;
     if (n > 0x7fffffff) return RKC_ENOTSUP;
-    int cur = 0;
-    HIP_OK(hipGetDevice(&cur));
-    if (cur != m->device) HIP_OK(hipSetDevice(m->device));
+    DeviceScope dev;
+    HIP_OK(dev.enter(m->device));
 
     hipStream_t st = (hipStream_t)o.stream;
     const size_t nS = (size_t)m->nS;
@@ -1123,9 +1138,8 @@ int rkc_graph_create(const rkc_mech *mc, size_t n, double *T, const double *P, d
     if (rc) return rc;
     if (n == 0 || !T || !P || !Y) return RKC_EINVAL;
     if (n > 0x7fffffff) return RKC_ENOTSUP;
-    int cur = 0;
-    HIP_OK(hipGetDevice(&cur));
-    if (cur != m->device) HIP_OK(hipSetDevice(m->device));
+    DeviceScope dev;
+    HIP_OK(dev.enter(m->device));
     rkc_graph *g = new (std::nothrow) rkc_graph();
     if (!g) return RKC_ENOMEM;
     g->device = m->device;
@@ -1156,7 +1170,6 @@ int rkc_graph_create(const rkc_mech *mc, size_t n, double *T, const double *P, d
                    "hipGraphInstantiate", __LINE__))
         rc = RKC_EDEVICE;
     if (cap) (void)hipStreamDestroy(cap);
-    if (cur != m->device) (void)hipSetDevice(cur);
     if (rc) {
         rkc_graph_destroy(g);
         return rc;
@@ -1182,9 +1195,8 @@ int rkc_autotune(const rkc_mech *mc, size_t n, const double *T, const double *P,
     if (rc) return rc;
     if (n == 0 || !T || !P || !Y) return RKC_EINVAL;
     if (n > 0x7fffffff) return RKC_ENOTSUP;
-    int cur = 0;
-    HIP_OK(hipGetDevice(&cur));
-    if (cur != m->device) HIP_OK(hipSetDevice(m->device));
+    DeviceScope dev;
+    HIP_OK(dev.enter(m->device));
     Choice ch;
     rc = choose_variant(m, o.lanes_per_cell, o.param_placement, &ch);
     if (rc) return rc;
@@ -1253,7 +1265,6 @@ int rkc_autotune(const rkc_mech *mc, size_t n, const double *T, const double *P,
     if (e1) (void)hipEventDestroy(e1);
     (void)hipStreamSynchronize(st);
     (void)hipFree(buf);
-    if (cur != m->device) (void)hipSetDevice(cur);
     if (rc) return rc;
     if (best_ms) *best_ms = best;
     return RKC_OK;

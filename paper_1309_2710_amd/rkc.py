@@ -238,6 +238,35 @@ def _check_shapes(mech, n, P, Y):
                          % (n, tuple(P.shape), tuple(Y.shape), mech.n_species))
 
 
+def _check_arrays(arrays, int32=False):
+    """Every array handed to the C ABI as a bare pointer: all numpy (host) or
+    all torch tensors on one GPU, C-contiguous, float64 (int32 for counts).
+    Raises TypeError/ValueError otherwise; returns True for torch tensors."""
+    dev = _is_torch(arrays[0])
+    if dev:
+        import torch
+        want = torch.int32 if int32 else torch.float64
+        d0 = arrays[0].device
+        for a in arrays:
+            if not _is_torch(a) or not a.is_cuda or a.device != d0:
+                raise TypeError("expected torch tensors on one GPU device")
+            if a.dtype != want or not a.is_contiguous():
+                raise TypeError("expected contiguous %s tensors" % want)
+    else:
+        want = np.int32 if int32 else np.float64
+        for a in arrays:
+            if not isinstance(a, np.ndarray):
+                raise TypeError("expected numpy arrays (or torch GPU tensors)")
+            if a.dtype != want or not a.flags.c_contiguous:
+                raise TypeError("expected C-contiguous %s arrays" % np.dtype(want).name)
+    return dev
+
+
+def _check_T(T):
+    if len(T.shape) != 1:
+        raise ValueError("T must be one-dimensional [n_cells]")
+
+
 def make_opts(method=RKC, s_max=1000, max_steps=1000000, lanes_per_cell=0,
               schedule=SCHED_AUTO, block_groups=0, grid_blocks=0, device_ptrs=False,
               stream=None, cell_counters=None, param_placement=PARAMS_AUTO):
@@ -276,14 +305,13 @@ def integrate(mech, T, P, Y, dt, rtol=1e-6, atol=1e-10, method=RKC, lanes_per_ce
     'stats' (dict), 'rc'.
     """
     L = lib()
-    dev = _is_torch(T)
+    dev = _check_arrays([T, P, Y])
+    _check_T(T)
     n = int(T.shape[0])
     _check_shapes(mech, n, P, Y)
     out = {}
     if dev:
         import torch
-        for a in (T, P, Y):
-            assert a.is_cuda and a.dtype == torch.float64 and a.is_contiguous()
         st_t = torch.empty(n, dtype=torch.int32, device=T.device) if status else None
         cn_t = torch.empty((n, NCOUNTERS), dtype=torch.int32, device=T.device) if counters else None
         ptrs = [ct.c_void_p(a.data_ptr()) for a in (T, P, Y)]
@@ -291,8 +319,6 @@ def integrate(mech, T, P, Y, dt, rtol=1e-6, atol=1e-10, method=RKC, lanes_per_ce
         cp = ct.c_void_p(cn_t.data_ptr()) if counters else None
         strm = _stream_handle(stream, [T])
     else:
-        for a in (T, P, Y):
-            assert isinstance(a, np.ndarray) and a.dtype == np.float64 and a.flags.c_contiguous
         st_t = np.empty(n, np.int32) if status else None
         cn_t = np.empty((n, NCOUNTERS), np.int32) if counters else None
         ptrs = [_np_ptr(a) for a in (T, P, Y)]
@@ -346,9 +372,13 @@ class Graph:
     def __init__(self, mech, T, P, Y, dt, rtol=1e-6, atol=1e-10, method=RKC, lanes_per_cell=0,
                  schedule=SCHED_AUTO, block_groups=0, grid_blocks=0, s_max=1000,
                  max_steps=1000000, status=None, param_placement=PARAMS_AUTO):
-        import torch
-        for a in (T, P, Y):
-            assert a.is_cuda and a.dtype == torch.float64 and a.is_contiguous()
+        if not _check_arrays([T, P, Y]):
+            raise TypeError("a graph records device arrays: torch GPU tensors expected")
+        _check_T(T)
+        _check_shapes(mech, int(T.shape[0]), P, Y)
+        if status is not None and (not _check_arrays([status], int32=True)
+                                   or tuple(status.shape) != (int(T.shape[0]),)):
+            raise ValueError("status must be an int32 GPU tensor [n_cells]")
         o = make_opts(method, s_max, max_steps, lanes_per_cell, schedule, block_groups,
                       grid_blocks, True, None, None, param_placement)
         h = ct.c_void_p()
@@ -390,9 +420,8 @@ def divergence(work, width=32, stride=1, stream=None):
     L = lib()
     n = int(work.shape[0])
     runs = (n + width - 1) // width
-    if _is_torch(work):
+    if _check_arrays([work], int32=True):
         import torch
-        assert work.is_cuda and work.dtype == torch.int32 and work.is_contiguous()
         st = int(work.stride(0)) if work.dim() == 2 else 1
         D = torch.empty(runs, dtype=torch.float64, device=work.device)
         o = make_opts(device_ptrs=True, stream=_stream_handle(stream, [work]))
@@ -411,18 +440,20 @@ def divergence(work, width=32, stride=1, stream=None):
 def rhs(mech, T, P, Y, lanes_per_cell=0, stream=None):
     """Source term f [n][nS+1] (column 0 = dT/dt) for numpy or torch GPU inputs."""
     L = lib()
+    _check_T(T)
     n = int(T.shape[0])
     _check_shapes(mech, n, P, Y)
     N = mech.n_species + 1
     if _is_torch(T):
         import torch
+        _check_arrays([T, P, Y])
         f = torch.empty((n, N), dtype=torch.float64, device=T.device)
         ptrs = [ct.c_void_p(a.data_ptr()) for a in (T, P, Y, f)]
         o = make_opts(lanes_per_cell=lanes_per_cell, device_ptrs=True,
                       stream=_stream_handle(stream, [T]))
     else:
         f = np.empty((n, N), np.float64)
-        ptrs = [_np_ptr(np.ascontiguousarray(a, np.float64)) for a in (T, P, Y)] + [_np_ptr(f)]
+        # host inputs are copied by the call: any float array is converted first
         keep = [np.ascontiguousarray(a, np.float64) for a in (T, P, Y)]
         ptrs = [_np_ptr(a) for a in keep] + [_np_ptr(f)]
         o = make_opts(lanes_per_cell=lanes_per_cell)
@@ -466,12 +497,14 @@ class Server:
         return mid.value
 
     def submit(self, mech_id, T, P, Y, dt, rtol=1e-6, atol=1e-10, method=RKC, status=None):
-        for a in (T, P, Y):
-            assert isinstance(a, np.ndarray) and a.dtype == np.float64 and a.flags.c_contiguous
+        if _check_arrays([T, P, Y]):
+            raise TypeError("the server takes host (numpy) arrays")
+        _check_T(T)
         n = int(T.shape[0])
-        assert Y.shape == (n, self._nS[mech_id])
-        if status is not None:
-            assert status.dtype == np.int32 and status.shape == (n,)
+        if tuple(P.shape) != (n,) or tuple(Y.shape) != (n, self._nS[mech_id]):
+            raise ValueError("shape mismatch: T [%d], P %s, Y %s" % (n, P.shape, Y.shape))
+        if status is not None and (_check_arrays([status], int32=True) or status.shape != (n,)):
+            raise ValueError("status must be an int32 numpy array [n_cells]")
         rid = ct.c_uint64()
         rc = lib().rkc_server_submit(self._h, int(mech_id), n, _np_ptr(T), _np_ptr(P), _np_ptr(Y),
                                      float(dt), float(rtol), float(atol), int(method),

@@ -112,3 +112,24 @@ def test_mech_create_rejects_bad_pressure_dependence_without_a_device():
     d, keep = rkc._mech_desc(m)
     h = ct.c_void_p()
     assert L.rkc_mech_create(ct.byref(d), ct.byref(h)) == rkc.EINVAL
+
+
+def test_binding_rejects_arrays_the_abi_cannot_take():
+    """Bare pointers carry no type or layout: the binding refuses, before any
+    call, what the kernels would misread (wrong dtype, strided, wrong rank)."""
+    class FakeMech:
+        n_species = 3
+        handle = None
+    T = np.full(4, 1200.0)
+    P = np.full(4, 1e5)
+    Y = np.full((4, 3), 1.0 / 3.0)
+    with pytest.raises(TypeError):
+        rkc.integrate(FakeMech(), T.astype(np.float32), P, Y, 1e-6)
+    with pytest.raises(TypeError):
+        rkc.integrate(FakeMech(), T, P, np.asfortranarray(np.full((4, 3), 0.5)), 1e-6)
+    with pytest.raises(TypeError):
+        rkc.integrate(FakeMech(), T, P, [[0.5] * 3] * 4, 1e-6)
+    with pytest.raises(ValueError):
+        rkc.integrate(FakeMech(), np.full((4, 1), 1200.0), P, Y, 1e-6)
+    with pytest.raises(TypeError):
+        rkc.divergence(np.zeros(8, np.int64))
