@@ -396,10 +396,12 @@ def study_crossover(args):
                 torch.cuda.synchronize()
                 t = time.perf_counter()
                 o = rkc.integrate(gm, T, P, Y, dt, c["rtol"], c["atol"], method=method,
-                                  stats=True, status=False)
+                                  stats=True, status=False, counters=True)
                 torch.cuda.synchronize()
                 wall = time.perf_counter() - t
+                # a launch lasts as long as its most expensive cell
                 res[name] = {"cell_odes_per_s": n / wall, "rhs_per_cell": o["stats"]["n_rhs"] / n,
+                             "rhs_max_cell": int(o["counters"][:, 0].max().item()),
                              "failed": o["stats"]["n_failed"]}
             row = {"set": "%dsp/%drx" % (mech["n_species"], mech["n_reactions"]), "dt": dt,
                    "cells": n, "rkc": res["rkc"], "rkck": res["rkck"],
