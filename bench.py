@@ -144,8 +144,10 @@ def main():
 
     import torch
 
+    from paper_1309_2710_amd import build as lib_build
     from paper_1309_2710_amd import rkc, synth
 
+    lib_build.ensure_built()   # load what is built; build only if nothing is
     if args.serve:
         serve(args)
         return

@@ -60,5 +60,14 @@ def build(verbose=False, jobs=None):
     return LIB
 
 
+def ensure_built():
+    """Build the library only if none is built (the tests, the smoke check and
+    the benchmark load what is there; build() always recompiles)."""
+    if not os.path.exists(LIB):
+        print("librkc.so not found: building it for %s" % ARCH, flush=True)
+        build()
+    return LIB
+
+
 if __name__ == "__main__":
     build(verbose="-v" in sys.argv)

@@ -11,3 +11,6 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU")
     config.addinivalue_line("markers", "slow: long CPU test")
+    # load what is built; build only if nothing is
+    from paper_1309_2710_amd import build as _build
+    _build.ensure_built()
