@@ -62,14 +62,16 @@ def rhs_flops(mech):
 
 def kernel_source_hash():
     """sha256 over the HIP sources of the library (host and device code) and
-    the build script that holds the compiler flags."""
+    the compiler flags and target it is built with."""
+    from paper_1309_2710_amd import build as lib_build
+
     d = os.path.join(ROOT, "paper_1309_2710_amd", "csrc")
     h = hashlib.sha256()
     for f in sorted(os.listdir(d)):
         if f.endswith((".h", ".hip")):
             h.update(f.encode())
             h.update(open(os.path.join(d, f), "rb").read())
-    h.update(open(os.path.join(ROOT, "paper_1309_2710_amd", "build.py"), "rb").read())
+    h.update(" ".join(lib_build.CFLAGS + [lib_build.ARCH]).encode())
     return h.hexdigest()
 
 
