@@ -71,7 +71,9 @@ def kernel_source_hash():
         if f.endswith((".h", ".hip")):
             h.update(f.encode())
             h.update(open(os.path.join(d, f), "rb").read())
-    h.update(" ".join(lib_build.CFLAGS + [lib_build.ARCH]).encode())
+    # include directories are absolute paths of this checkout: left out
+    flags = [f for f in lib_build.CFLAGS if not f.startswith("-I")]
+    h.update(" ".join(flags + [lib_build.ARCH]).encode())
     return h.hexdigest()
 
 
