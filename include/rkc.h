@@ -76,6 +76,11 @@ extern "C" {
                                     global memory through the caches; RKC_ENOTSUP
                                     when no such variant is compiled for the shape */
 
+/* Largest n_cells of one call (2^31 - 2^20): cell indices and work-queue
+ * claims stay within int32 with room for every lane group of the grid;
+ * larger calls return RKC_ENOTSUP. */
+#define RKC_MAX_CELLS 2146435072
+
 /* Number of int32 per cell in opts->cell_counters. */
 #define RKC_NCOUNTERS 8
 /* Column order of opts->cell_counters rows. */
@@ -264,7 +269,7 @@ int rkc_graph_destroy(rkc_graph *graph);
  * Arrays are host pointers unless opts->device_ptrs (then device pointers,
  * enqueued on opts->stream); opts may be NULL.  Runs on the current device.
  * Returns RKC_OK, RKC_EINVAL (stride or width < 1, NULL array), RKC_ENOMEM,
- * RKC_ENOTSUP (sizes beyond 2^31 cells) or RKC_EDEVICE; n_cells = 0 is a no-op. */
+ * RKC_ENOTSUP (n_cells above RKC_MAX_CELLS) or RKC_EDEVICE; n_cells = 0 is a no-op. */
 int rkc_divergence(size_t n_cells, const int32_t *work, int32_t stride, int32_t width,
                    double *D, const rkc_opts *opts);
 

@@ -963,7 +963,7 @@ int rkc_rhs(const rkc_mech *mc, size_t n, const double *T, const double *P, cons
     if (opts) o = *opts; else rkc_opts_default(&o);
     if (n == 0) return RKC_OK;
     if (!T || !P || !Y || !f) return RKC_EINVAL;
-    if (n > 0x7fffffff) return RKC_ENOTSUP;
+    if (n > RKC_MAX_CELLS) return RKC_ENOTSUP;
     DeviceScope dev;
     HIP_OK(dev.enter(m->device));
     Choice ch;
@@ -1021,7 +1021,7 @@ int rkc_integrate(const rkc_mech *mc, size_t n, double *T, const double *P, doub
     if (stats) std::memset(stats, 0, sizeof(*stats));
     if (n == 0) return RKC_OK;
     if (!T || !P || !Y) return RKC_EINVAL;
-    if (n > 0x7fffffff) return RKC_ENOTSUP;
+    if (n > RKC_MAX_CELLS) return RKC_ENOTSUP;
     DeviceScope dev;
     HIP_OK(dev.enter(m->device));
 
@@ -1137,7 +1137,7 @@ int rkc_graph_create(const rkc_mech *mc, size_t n, double *T, const double *P, d
     int rc = rkchost::check_integrate_args(dt, rtol, atol, o);
     if (rc) return rc;
     if (n == 0 || !T || !P || !Y) return RKC_EINVAL;
-    if (n > 0x7fffffff) return RKC_ENOTSUP;
+    if (n > RKC_MAX_CELLS) return RKC_ENOTSUP;
     DeviceScope dev;
     HIP_OK(dev.enter(m->device));
     rkc_graph *g = new (std::nothrow) rkc_graph();
@@ -1194,7 +1194,7 @@ int rkc_autotune(const rkc_mech *mc, size_t n, const double *T, const double *P,
     int rc = rkchost::check_integrate_args(dt, rtol, atol, o);
     if (rc) return rc;
     if (n == 0 || !T || !P || !Y) return RKC_EINVAL;
-    if (n > 0x7fffffff) return RKC_ENOTSUP;
+    if (n > RKC_MAX_CELLS) return RKC_ENOTSUP;
     DeviceScope dev;
     HIP_OK(dev.enter(m->device));
     Choice ch;

@@ -275,7 +275,7 @@ int rkc_server_submit(rkc_server *s, int32_t mech_id, size_t n, double *T, const
     o.method = method;
     int rc = rkchost::check_integrate_args(dt, rtol, atol, o);
     if (rc) return rc;
-    if (n > 0x7fffffff) return RKC_ENOTSUP;
+    if (n > RKC_MAX_CELLS) return RKC_ENOTSUP;
     if (n > 0 && (!T || !P || !Y)) return RKC_EINVAL;
     rkcsrv::Request r;
     r.mech = mech_id;

@@ -25,6 +25,7 @@ RKC, RKCK = 0, 1
 SCHED_AUTO, SCHED_PLAIN, SCHED_PERSISTENT = 0, 1, 2
 PARAMS_AUTO, PARAMS_REGISTERS, PARAMS_LDS, PARAMS_GLOBAL = 0, 1, 2, 3
 NCOUNTERS = 8
+MAX_CELLS = 2146435072          # RKC_MAX_CELLS: largest n_cells of one call
 COUNTER_FIELDS = ["n_rhs", "n_steps", "n_reject", "n_sigma", "s_max_used", "s_hash", "status",
                   "n_power_iter"]
 

@@ -133,3 +133,9 @@ def test_binding_rejects_arrays_the_abi_cannot_take():
         rkc.integrate(FakeMech(), np.full((4, 1), 1200.0), P, Y, 1e-6)
     with pytest.raises(TypeError):
         rkc.divergence(np.zeros(8, np.int64))
+
+
+def test_binding_constants_match_the_header():
+    txt = open(HDR).read()
+    assert int(re.search(r"#define RKC_MAX_CELLS (\d+)", txt).group(1)) == rkc.MAX_CELLS == 2**31 - 2**20
+    assert int(re.search(r"#define RKC_NCOUNTERS (\d+)", txt).group(1)) == rkc.NCOUNTERS

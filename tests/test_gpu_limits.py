@@ -77,3 +77,21 @@ def test_one_species_more_is_refused(R):
     with pytest.raises(R.RkcError) as e:
         R.integrate(gm, st["T"].copy(), st["P"], Y, 1e-6)
     assert e.value.code == R.ENOTSUP
+
+
+def test_cell_count_above_the_limit_is_refused(R):
+    """One cell more than RKC_MAX_CELLS is refused before any array is read
+    (the arrays passed here are far smaller than the count)."""
+    import ctypes as ct
+    _say("n_cells above RKC_MAX_CELLS refused")
+    gm = R.Mechanism(_mech(31))
+    x = np.zeros(64)
+    o = R.make_opts()
+    big = R.MAX_CELLS + 1
+    L = R.lib()
+    rc = L.rkc_integrate(gm.handle, big, R._np_ptr(x), R._np_ptr(x), R._np_ptr(x), 1e-6, 1e-6,
+                         1e-10, ct.byref(o), None, None)
+    assert rc == R.ENOTSUP
+    rc = L.rkc_rhs(gm.handle, big, R._np_ptr(x), R._np_ptr(x), R._np_ptr(x), R._np_ptr(x),
+                   ct.byref(o))
+    assert rc == R.ENOTSUP
