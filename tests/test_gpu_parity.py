@@ -59,7 +59,7 @@ def test_rhs_parity(R, cfg, G):
 
 def max_flips(cfg, n):
     # long-horizon 111-species workload: ~1000 accepted steps per cell
-    return max(2, int(0.15 * n)) if cfg == "c4" else max(1, n // 100)
+    return max(2, int(0.15 * n)) if cfg in ("c4", "c4p") else max(1, n // 100)
 
 
 # RKCK runs in the paper's nonstiff setting for it (Sec. 3.1: global step
@@ -198,6 +198,18 @@ def test_full_size_c4_sampled(R):
     """111sp/1566rx at its full 65536 cells (64 lanes, two state slots per
     lane, 10-term gather segments)."""
     _full_size_sampled(R, "c4", 32)
+
+
+def test_full_size_c3p_sampled(R):
+    """53sp/634rx with third-body and falloff pairs at its full 131072 cells
+    (32-lane groups, the automatic choice for this set)."""
+    _full_size_sampled(R, "c3p", 32)
+
+
+def test_full_size_c4p_sampled(R):
+    """111sp/1566rx with third-body and falloff pairs at its full 65536 cells
+    (parameters in global memory, the automatic choice for this set)."""
+    _full_size_sampled(R, "c4p", 16)
 
 
 def test_ten_consecutive_steps_c3(R):
