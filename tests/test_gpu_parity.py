@@ -157,19 +157,23 @@ def test_edge_cases(R):
     assert (out["status"] == R.CELL_MAXSTEPS).all() and (co["status"] == O.MAXSTEPS).all()
 
 
-def _full_size_sampled(R, cfg, n_sample):
+def _full_size_sampled(R, cfg, n_sample, method=O.RKC):
     """A workload at its full cell count, device-resident, in the launch
-    configuration the benchmark uses; the oracle checks a strided sample."""
+    configuration the benchmark uses; the oracle checks a strided sample.
+    RKCK runs in its nonstiff setting (global step and tolerance above)."""
     import torch
     gm, om = mech(R, cfg)
-    c = synth.CONFIGS[cfg]
+    c = dict(synth.CONFIGS[cfg])
+    if method == O.RKCK:
+        c["dt"], c["rtol"] = RKCK_DT, RKCK_TOL
     st = synth.config_states(cfg)
     n = st["T"].shape[0]
-    _say("full", cfg, n, "cells")
+    _say("full", cfg, n, "cells, method", method)
     T = torch.from_numpy(st["T"]).cuda()
     P = torch.from_numpy(st["P"]).cuda()
     Y = torch.from_numpy(st["Y"]).cuda()
-    out = R.integrate(gm, T, P, Y, c["dt"], c["rtol"], c["atol"], counters=True, stats=True)
+    out = R.integrate(gm, T, P, Y, c["dt"], c["rtol"], c["atol"], method=method, counters=True,
+                      stats=True)
     torch.cuda.synchronize()
     Tg, Yg = T.cpu().numpy(), Y.cpu().numpy()
     cg = out["counters"].cpu().numpy()
@@ -178,7 +182,7 @@ def _full_size_sampled(R, cfg, n_sample):
     assert np.abs(Yg.sum(1) - st["Y"].sum(1)).max() <= 1e-12
     idx = np.arange(0, n, n // n_sample)[:n_sample]
     To, Yo, co = om.integrate(st["T"][idx], st["P"][idx], st["Y"][idx], c["dt"], c["rtol"],
-                              c["atol"], threads=THREADS)
+                              c["atol"], method=method, threads=THREADS)
     rep = PT.check(Tg[idx], Yg[idx], cg[idx], To, Yo, co, c["rtol"], c["atol"],
                    max_flips(cfg, n_sample))
     _say(rep)
@@ -210,6 +214,11 @@ def test_full_size_c4p_sampled(R):
     """111sp/1566rx with third-body and falloff pairs at its full 65536 cells
     (parameters in global memory, the automatic choice for this set)."""
     _full_size_sampled(R, "c4p", 16)
+
+
+def test_full_size_rkck_c2_sampled(R):
+    """RKCK over the 13-species set's full 262144 cells (persistent schedule)."""
+    _full_size_sampled(R, "c2", 64, method=O.RKCK)
 
 
 def test_ten_consecutive_steps_c3(R):
