@@ -283,16 +283,20 @@ __device__ __forceinline__ double unpack_c(const double *C, uint32_t id, int s) 
     return C[(id >> (10 * s)) & 1023u];
 }
 
-// exp(x) for |x| < 1e9: Cody & Waite reduction x = n ln2 + r, |r| <= ln2/2,
-// with ln2 split into its double rounding and the remainder, then
-// exp(r) = 1 + r + r^2 q(r) with q a degree-9 Chebyshev fit of
-// (exp(r) - 1 - r)/r^2 on the reduced interval (relative error below 1.6e-17;
-// fit_exp_poly.py prints the coefficients), by Horner, scaled by 2^n.
-// Underflows to exactly 0 below about -745; NaN propagates.  Within about one
-// ulp; written so every Horner step is one FMA.  n is rounded by adding
-// 1.5 * 2^52 inside the FMA that forms x/ln2: the sum's unit in the last
-// place is 1, so its low 32 bits are n in two's complement (|n| < 2^31) and
-// serve as the exponent of the final scaling without a conversion.
+// exp(x): Cody & Waite reduction x = n ln2 + r, |r| <= ln2/2, with ln2 split
+// into its double rounding and the remainder, then exp(r) = 1 + r + r^2 q(r)
+// with q a degree-9 Chebyshev fit of (exp(r) - 1 - r)/r^2 on the reduced
+// interval (relative error below 1.6e-17; fit_exp_poly.py prints the
+// coefficients), by Horner, scaled by 2^n.  Within about one ulp; written so
+// every Horner step is one FMA.  n is rounded by adding 1.5 * 2^52 inside the
+// FMA that forms x/ln2.  The exponent of the final scaling is n converted to
+// int32 with saturation (v_cvt_i32_f64 clamps out-of-range values), so for
+// every |x| < 1e16 the result is exact to the above bound: 0 below about
+// -745, +inf above about 709.8 (there |r| stays below 0.3, as the rounding
+// error of n ln2 is far below ln2 / 2); NaN propagates (the conversion gives
+// 0, the polynomial NaN).  Callers keep |x| below 1e16: the Arrhenius
+// argument does for any temperature above 1e-10 K, the Troe terms through the
+// bounds the host puts on 1/T*** , 1/T* and T**.
 struct ExpK {
     double log2e, shift, ln2hi, ln2lo, c[10];
 };
@@ -305,6 +309,14 @@ __host__ __device__ constexpr ExpK exp_k() {
                  0.5000000000000001}};
 }
 
+// n (an integral double) to int32, saturating at the int32 range (the
+// hardware conversion clamps; NaN gives 0).
+__device__ __forceinline__ int cvt_sat_i32(double n) {
+    int i;
+    asm("v_cvt_i32_f64 %0, %1" : "=v"(i) : "v"(n));
+    return i;
+}
+
 __device__ __forceinline__ double exp_cw(double x, const ExpK &k) {
     const double t = __builtin_fma(x, k.log2e, k.shift);
     const double n = t - k.shift;
@@ -314,7 +326,7 @@ __device__ __forceinline__ double exp_cw(double x, const ExpK &k) {
     for (int i = 1; i < 10; ++i) q = __builtin_fma(q, r, k.c[i]);
     q = __builtin_fma(q, r, 1.0);
     q = __builtin_fma(q, r, 1.0);
-    return __builtin_ldexp(q, (int)(uint32_t)__double_as_longlong(t));
+    return __builtin_ldexp(q, cvt_sat_i32(n));
 }
 
 __device__ __forceinline__ double exp_cw(double x) { return exp_cw(x, exp_k()); }

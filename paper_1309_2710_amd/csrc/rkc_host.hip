@@ -19,6 +19,7 @@ namespace {
 constexpr double R_J = 8.31446261815324;   // J/(mol K)
 using rkchost::AGG_N;
 constexpr double LNA_ZERO = -1e4;          // ln A of a reaction whose rate is identically 0
+constexpr double TROE_BOUND = 1e10;        // largest 1/T***, 1/T* and T** passed to the kernels
 
 // Device tables that depend on the lane-group shape: the species table is
 // laid out with stride NK, the gather is balanced over G lanes.
@@ -862,10 +863,16 @@ int rkc_mech_create(const rkc_mech_desc *d, rkc_mech **out) {
             }
             if (kind == RKC_PDEP_TROE) {
                 const double *t = d->troe + 4 * (size_t)j;
+                // The kernels evaluate exp(-T / T***), exp(-T / T*) and
+                // exp(-T** / T) with an exponential exact for arguments of
+                // magnitude below 1e16.  Sentinels such as T*** = 1e-30 or
+                // T** = 1e30 ("term off") are bounded to TROE_BOUND, which
+                // leaves every value unchanged between 1e-6 K and 1e6 K: the
+                // term is exactly 0 there either way.
                 u.pd[8] = t[0];
-                u.pd[9] = 1.0 / t[1];
-                u.pd[10] = 1.0 / t[2];
-                u.pd[11] = t[3];
+                u.pd[9] = std::min(1.0 / t[1], TROE_BOUND);
+                u.pd[10] = std::min(1.0 / t[2], TROE_BOUND);
+                u.pd[11] = std::min(t[3], TROE_BOUND);
             }
         }
         for (int i = 0; i < nS; ++i) {

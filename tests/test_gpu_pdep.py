@@ -87,3 +87,42 @@ def test_closed_forms_on_the_gpu(R):
     lind = _pdep(mechs.a_to_b(kinf, W), [2], k0=[k0])
     ratio = _gpu_rate_A(R, troe, T, P, [0.5, 0.5]) / _gpu_rate_A(R, lind, T, P, [0.5, 0.5])
     assert ratio == pytest.approx(Fc, rel=1e-12)
+
+
+@pytest.mark.parametrize("troe", [[0.5, 1e-30, 1e30, 0.0], [0.3, 1e-30, 1e-30, 1e30],
+                                  [0.7, 1e30, 1e-30, 1e-30]])
+def test_troe_sentinel_temperatures_against_oracle(R, troe):
+    """Troe temperatures used as 'term off' sentinels (1e-30 and 1e30 K): the
+    centre value's exponentials have arguments far beyond the exponential's
+    int32 exponent range (-T/1e-30 is -1e33), where the result is exactly 0
+    or 1; over 800-2400 K the source term must equal the oracle's."""
+    _say("troe sentinels", troe)
+    kinf, k0 = 2.0e5, 4.0e10
+    m = _pdep(mechs.a_to_b(kinf, 10.0), [3], k0=[k0], troe=[troe])
+    n = 97
+    T = np.linspace(800.0, 2400.0, n)
+    P = np.full(n, ATM)
+    Y = np.tile([0.45, 0.55], (n, 1))
+    fg = R.rhs(R.Mechanism(m), T, P, Y, lanes_per_cell=8)
+    fo = O.Model(m).rhs(T, P, Y)
+    assert np.isfinite(fo).all()
+    assert np.isfinite(fg).all(), fg[~np.isfinite(fg).all(1)][:3]
+    e = np.abs(fg[:, 1] - fo[:, 1]) / np.abs(fo[:, 1])
+    _say("max rel err", e.max())
+    assert e.max() <= 1e-12
+
+
+def test_arrhenius_argument_below_int32_exponent_range(R):
+    """-E/(R T) far below -1.5e9 (T of 1e-8 to 1e-4 K, E/R 2.4e4 K): the rate
+    constant is exactly 0, as in the oracle, not a wrapped exponent."""
+    _say("arrhenius tiny T")
+    m = mechs.tiny([10.0, 10.0], [([0], [1], 1e13, 0.0, 2.0e5)])
+    T = np.array([1e-8, 1e-7, 1e-6, 1e-5, 1e-4, 1.0, 1000.0])
+    n = len(T)
+    P = np.full(n, ATM)
+    Y = np.tile([0.5, 0.5], (n, 1))
+    fg = R.rhs(R.Mechanism(m), T, P, Y, lanes_per_cell=8)
+    fo = O.Model(m).rhs(T, P, Y)
+    assert np.isfinite(fg).all()
+    assert np.array_equal(fg[:-1], fo[:-1])   # exactly zero rates
+    assert fg[-1, 1] == pytest.approx(fo[-1, 1], rel=1e-13)
