@@ -38,29 +38,49 @@ class Counters(ct.Structure):
 COUNTER_FIELDS = [f[0] for f in Counters._fields_]
 
 
+class Step(ct.Structure):
+    _fields_ = [("t", ct.c_double), ("h", ct.c_double), ("err", ct.c_double),
+                ("sigma", ct.c_double), ("y", ct.c_double * 3), ("s", ct.c_int32),
+                ("new_sigma", ct.c_int32), ("accepted", ct.c_int32), ("pad", ct.c_int32)]
+
+
+def _declare(L):
+    """Argument and result types of the library's entry points."""
+    L.orc_model_create.restype = ct.c_void_p
+    L.orc_model_create.argtypes = [ct.POINTER(_Mech)]
+    L.orc_model_destroy.argtypes = [ct.c_void_p]
+    L.orc_rhs.argtypes = [ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_void_p, ct.c_void_p]
+    L.orc_rkc_coeffs.argtypes = [ct.c_int] + [ct.c_void_p] * 4
+    L.orc_rkc_fixed_step.argtypes = [ct.c_void_p, ct.c_double, ct.c_void_p, ct.c_double,
+                                     ct.c_int]
+    L.orc_rkck_fixed_step.argtypes = [ct.c_void_p, ct.c_double, ct.c_void_p, ct.c_double,
+                                      ct.c_void_p]
+    L.orc_sigma.restype = ct.c_double
+    L.orc_sigma.argtypes = [ct.c_void_p, ct.c_double, ct.c_void_p, ct.POINTER(ct.c_int)]
+    L.orc_cell_trace.restype = ct.c_int
+    L.orc_cell_trace.argtypes = [ct.c_void_p, ct.c_int, ct.c_double, ct.c_void_p,
+                                 ct.c_double, ct.c_double, ct.c_double, ct.c_int, ct.c_int,
+                                 ct.c_void_p, ct.c_void_p, ct.c_int, ct.POINTER(ct.c_int)]
+    L.orc_integrate.argtypes = [ct.c_void_p, ct.c_int, ct.c_int, ct.c_void_p, ct.c_void_p,
+                                ct.c_void_p, ct.c_double, ct.c_double, ct.c_double,
+                                ct.c_int, ct.c_int, ct.c_void_p, ct.c_int]
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
         path = _build.LIB
         if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_build.SRC):
             _build.build()
-        L = ct.CDLL(path)
-        L.orc_model_create.restype = ct.c_void_p
-        L.orc_model_create.argtypes = [ct.POINTER(_Mech)]
-        L.orc_model_destroy.argtypes = [ct.c_void_p]
-        L.orc_rhs.argtypes = [ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_void_p, ct.c_void_p]
-        L.orc_rkc_coeffs.argtypes = [ct.c_int] + [ct.c_void_p] * 4
-        L.orc_rkc_fixed_step.argtypes = [ct.c_void_p, ct.c_double, ct.c_void_p, ct.c_double,
-                                         ct.c_int]
-        L.orc_rkck_fixed_step.argtypes = [ct.c_void_p, ct.c_double, ct.c_void_p, ct.c_double,
-                                          ct.c_void_p]
-        L.orc_sigma.restype = ct.c_double
-        L.orc_sigma.argtypes = [ct.c_void_p, ct.c_double, ct.c_void_p, ct.POINTER(ct.c_int)]
-        L.orc_integrate.argtypes = [ct.c_void_p, ct.c_int, ct.c_int, ct.c_void_p, ct.c_void_p,
-                                    ct.c_void_p, ct.c_double, ct.c_double, ct.c_double,
-                                    ct.c_int, ct.c_int, ct.c_void_p, ct.c_int]
-        _lib = L
+        _lib = _declare(ct.CDLL(path))
     return _lib
+
+
+def load_variant(path):
+    """A separately built copy of the oracle library (tests that plant a
+    mistake, or change one rounding, in a copy of the source)."""
+    return _declare(ct.CDLL(path))
 
 
 def _p(a):
@@ -70,8 +90,9 @@ def _p(a):
 class Model:
     """A mechanism loaded into the oracle (holds references to its arrays)."""
 
-    def __init__(self, mech):
-        L = lib()
+    def __init__(self, mech, library=None):
+        L = library if library is not None else lib()
+        self._L = L
         self.n_species = int(mech["n_species"])
         self.n_reactions = int(mech["n_reactions"])
         self._keep = {
@@ -102,8 +123,8 @@ class Model:
         self._h = L.orc_model_create(ct.byref(self._m))
 
     def __del__(self):
-        if getattr(self, "_h", None) and _lib is not None:
-            _lib.orc_model_destroy(self._h)
+        if getattr(self, "_h", None) and getattr(self, "_L", None) is not None:
+            self._L.orc_model_destroy(self._h)
             self._h = None
 
     @property
@@ -119,7 +140,7 @@ class Model:
         y[:, 1:] = np.asarray(Y, dtype=np.float64).reshape(n, self.n_species)
         P = np.ascontiguousarray(np.broadcast_to(np.asarray(P, dtype=np.float64), (n,)))
         f = np.empty_like(y)
-        lib().orc_rhs(self._h, n, _p(P), _p(y), _p(f))
+        self._L.orc_rhs(self._h, n, _p(P), _p(y), _p(f))
         return f
 
     def integrate(self, T, P, Y, dt, rtol=1e-6, atol=1e-10, method=RKC, s_max=1000,
@@ -132,28 +153,49 @@ class Model:
         cnt = (Counters * max(n, 1))()
         if threads is None:
             threads = min(os.cpu_count() or 1, 16)
-        lib().orc_integrate(self._h, int(method), n, _p(P), _p(T), _p(Y), float(dt),
+        self._L.orc_integrate(self._h, int(method), n, _p(P), _p(T), _p(Y), float(dt),
                             float(rtol), float(atol), int(s_max), int(max_steps),
                             ct.cast(cnt, ct.c_void_p), int(threads))
         arr = np.ctypeslib.as_array(cnt)[:n]
         c = {f: np.array([getattr(x, f) for x in cnt[:n]], dtype=np.int64) for f in COUNTER_FIELDS}
         return T, Y, c
 
+    def trace(self, y, P, dt, rtol=1e-6, atol=1e-10, method=RKC, s_max=1000,
+              max_steps=1000000, cap=200000):
+        """One cell (y = [T, Y...]) integrated over [0, dt] with every attempted
+        step recorded.  Returns (y_out, counters dict, steps dict of arrays:
+        t, h, err, sigma, y [n][3], s, new_sigma, accepted)."""
+        y = np.array(y, dtype=np.float64, copy=True).reshape(-1)
+        assert y.shape[0] == self.N
+        buf = (Step * cap)()
+        cnt = Counters()
+        n = ct.c_int(0)
+        self._L.orc_cell_trace(self._h, int(method), float(P), _p(y), float(dt), float(rtol),
+                             float(atol), int(s_max), int(max_steps), ct.byref(cnt),
+                             ct.cast(buf, ct.c_void_p), int(cap), ct.byref(n))
+        m = min(n.value, cap)
+        steps = {f: np.array([getattr(buf[i], f) for i in range(m)])
+                 for f in ("t", "h", "err", "sigma", "s", "new_sigma", "accepted")}
+        steps["y"] = np.array([list(buf[i].y) for i in range(m)]).reshape(m, 3)
+        steps["accepted"] = steps["accepted"].astype(bool)
+        steps["new_sigma"] = steps["new_sigma"].astype(bool)
+        return y, {f: getattr(cnt, f) for f in COUNTER_FIELDS}, steps
+
     def rkc_fixed_step(self, y, P, h, s):
         y = np.array(y, dtype=np.float64, copy=True)
-        lib().orc_rkc_fixed_step(self._h, float(P), _p(y), float(h), int(s))
+        self._L.orc_rkc_fixed_step(self._h, float(P), _p(y), float(h), int(s))
         return y
 
     def rkck_fixed_step(self, y, P, h):
         y = np.array(y, dtype=np.float64, copy=True)
         y4 = np.empty_like(y)
-        lib().orc_rkck_fixed_step(self._h, float(P), _p(y), float(h), _p(y4))
+        self._L.orc_rkck_fixed_step(self._h, float(P), _p(y), float(h), _p(y4))
         return y, y4
 
     def sigma(self, y, P):
         y = np.ascontiguousarray(y, dtype=np.float64)
         it = ct.c_int(0)
-        s = lib().orc_sigma(self._h, float(P), _p(y), ct.byref(it))
+        s = self._L.orc_sigma(self._h, float(P), _p(y), ct.byref(it))
         return s, it.value
 
 

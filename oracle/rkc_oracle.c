@@ -84,6 +84,33 @@ typedef struct {
     int32_t n_rhs, n_steps, n_reject, n_sigma, s_max_used, s_hash, status, n_power_iter;
 } orc_counters;
 
+/* One attempted step, for the pins of the step-size control (test use):
+ * t and h of the attempt, the stage count s (RKC; 0 for RKCK), the error
+ * measure (RKC: weighted RMS norm of E:rmsE; RKCK: the largest
+ * |Delta_i / Delta_0,i|), the spectral radius estimate in use (RKC), whether
+ * the estimate was recomputed just before this attempt, whether the attempt
+ * was accepted, and the first three state components after it (the accepted
+ * state; on rejection the state the attempt started from). */
+typedef struct {
+    double t, h, err, sigma;
+    double y[3];
+    int32_t s, new_sigma, accepted, pad;
+} orc_step;
+
+typedef struct {
+    orc_step *buf;
+    int cap, n;
+} orc_trace;
+
+static void trace_put(orc_trace *tr, double t, double h, double err, double sigma, int s,
+                      int new_sigma, int accepted, const double *y, int N) {
+    if (!tr || tr->n >= tr->cap) { if (tr) tr->n += 1; return; }
+    orc_step *e = &tr->buf[tr->n++];
+    e->t = t; e->h = h; e->err = err; e->sigma = sigma;
+    for (int i = 0; i < 3; ++i) e->y[i] = (i < N) ? y[i] : 0.0;
+    e->s = s; e->new_sigma = new_sigma; e->accepted = accepted; e->pad = 0;
+}
+
 static int count_in(const int32_t *slots, int sp) {
     int c = 0;
     for (int s = 0; s < 3; ++s) c += (slots[s] == sp);
@@ -349,9 +376,10 @@ static void hash_s(orc_counters *cnt, int s) {
 
 /* ---------------------------------------------------------------- RKC ---- */
 
-/* Integrate one cell over [0, dt] with RKC; y (length N) is overwritten. */
-int orc_rkc_cell(const orc_model *md, double P, double *y, double dt, double rtol,
-                 double atol, int s_max, int max_steps, orc_counters *cnt) {
+/* Integrate one cell over [0, dt] with RKC; y (length N) is overwritten.
+ * tr (may be NULL) receives every attempted step. */
+static int rkc_cell(const orc_model *md, double P, double *y, double dt, double rtol,
+                    double atol, int s_max, int max_steps, orc_counters *cnt, orc_trace *tr) {
     const int N = md->m.n_species + 1;
     memset(cnt, 0, sizeof(*cnt));
     if (bad_input(y, P, N)) { cnt->status = ORC_BADINPUT; return ORC_BADINPUT; }
@@ -387,7 +415,7 @@ int orc_rkc_cell(const orc_model *md, double P, double *y, double dt, double rto
     if (h > t_end) h = t_end;
 
     double t = 0.0, h_prev = 0.0, err_prev = 0.0;
-    int need_sigma = 0, since_sigma = 0, predictive = 0;
+    int need_sigma = 0, since_sigma = 0, predictive = 0, fresh_sigma = 1;
     for (;;) {
         if (cnt->n_steps + cnt->n_reject >= max_steps) { status = ORC_MAXSTEPS; break; }
         if (need_sigma) {
@@ -395,7 +423,9 @@ int orc_rkc_cell(const orc_model *md, double P, double *y, double dt, double rto
             if (!isfinite(sigma)) { status = ORC_NONFINITE; break; }
             need_sigma = 0;
             since_sigma = 0;
+            fresh_sigma = 1;
         }
+        const double t_attempt = t;
         int last = (h >= t_end - t);
         if (last) h = t_end - t;
         int s = 1 + (int)floor(sqrt(1.0 + 1.54 * h * sigma));
@@ -424,7 +454,10 @@ int orc_rkc_cell(const orc_model *md, double P, double *y, double dt, double rto
         for (int i = 0; i < N; ++i) del[i] = 0.8 * (y[i] - wm1[i]) + 0.4 * h * (f0[i] + f1[i]);
         double err = rms_err(del, y, wm1, rtol, atol, N);
         /* a trial step whose error is not finite is rejected with the largest shrink */
-        if (err <= 1.0) {
+        const int accept = (err <= 1.0);
+        trace_put(tr, t_attempt, h, err, sigma, s, fresh_sigma, accept, accept ? wm1 : y, N);
+        fresh_sigma = 0;
+        if (accept) {
             cnt->n_steps += 1;
             for (int i = 0; i < N; ++i) { y[i] = wm1[i]; f0[i] = f1[i]; }
             if (last) { t = t_end; break; }
@@ -456,6 +489,17 @@ done:
     free(cm); free(buf); ws_free(&c.ws);
     return status;
 }
+
+int orc_rkc_cell(const orc_model *md, double P, double *y, double dt, double rtol,
+                 double atol, int s_max, int max_steps, orc_counters *cnt) {
+    return rkc_cell(md, P, y, dt, rtol, atol, s_max, max_steps, cnt, NULL);
+}
+
+/* RKC or RKCK on one cell with every attempted step recorded in trace[0..cap)
+ * (*n_trace receives the number of attempts, which may exceed cap). */
+int orc_cell_trace(const orc_model *md, int method, double P, double *y, double dt, double rtol,
+                   double atol, int s_max, int max_steps, orc_counters *cnt, orc_step *trace,
+                   int cap, int *n_trace);
 
 /* --------------------------------------------------------------- RKCK ---- */
 
@@ -507,8 +551,8 @@ static void rkck_step(ctx_t *c, const double *y, double h, double *k, double *z,
     }
 }
 
-int orc_rkck_cell(const orc_model *md, double P, double *y, double dt, double rtol,
-                  int max_steps, orc_counters *cnt) {
+static int rkck_cell(const orc_model *md, double P, double *y, double dt, double rtol,
+                     int max_steps, orc_counters *cnt, orc_trace *tr) {
     const int N = md->m.n_species + 1;
     memset(cnt, 0, sizeof(*cnt));
     if (bad_input(y, P, N)) { cnt->status = ORC_BADINPUT; return ORC_BADINPUT; }
@@ -537,6 +581,7 @@ int orc_rkck_cell(const orc_model *md, double P, double *y, double dt, double rt
         }
         if (nonfinite) errmax = INFINITY;
         /* a trial step whose error is not finite is rejected with the largest shrink */
+        trace_put(tr, t, h, errmax, 0.0, 0, 0, errmax <= 1.0, errmax <= 1.0 ? y5 : y, N);
         if (errmax <= 1.0) {
             cnt->n_steps += 1;
             for (int i = 0; i < N; ++i) y[i] = y5[i];
@@ -556,6 +601,21 @@ int orc_rkck_cell(const orc_model *md, double P, double *y, double dt, double rt
     cnt->status = status;
     free(buf); ws_free(&c.ws);
     return status;
+}
+
+int orc_rkck_cell(const orc_model *md, double P, double *y, double dt, double rtol,
+                  int max_steps, orc_counters *cnt) {
+    return rkck_cell(md, P, y, dt, rtol, max_steps, cnt, NULL);
+}
+
+int orc_cell_trace(const orc_model *md, int method, double P, double *y, double dt, double rtol,
+                   double atol, int s_max, int max_steps, orc_counters *cnt, orc_step *trace,
+                   int cap, int *n_trace) {
+    orc_trace tr = {trace, cap, 0};
+    int st = (method == ORC_RKCK) ? rkck_cell(md, P, y, dt, rtol, max_steps, cnt, &tr)
+                                  : rkc_cell(md, P, y, dt, rtol, atol, s_max, max_steps, cnt, &tr);
+    if (n_trace) *n_trace = tr.n;
+    return st;
 }
 
 /* ----------------------------------------------- fixed-step primitives ---- */
