@@ -53,7 +53,8 @@ def test_global_tables_equal_lds_and_oracle(R):
     c = synth.CONFIGS["c4"]
     To, Yo, co = O.Model(m).integrate(st["T"], st["P"], st["Y"], c["dt"], c["rtol"], c["atol"],
                                       threads=16)
-    PT.check(Tg, Yg, og["counters"], To, Yo, co, c["rtol"], c["atol"], max(2, int(0.15 * 24)))
+    PT.check(Tg, Yg, og["counters"], To, Yo, co, c["rtol"], c["atol"], PT.max_flips("c4", 24),
+             long_set=True)
 
 
 def test_global_tables_with_falloff(R):
@@ -72,7 +73,8 @@ def test_global_tables_with_falloff(R):
     c = synth.CONFIGS["c4p"]
     To, Yo, co = O.Model(m).integrate(st["T"], st["P"], st["Y"], c["dt"], c["rtol"], c["atol"],
                                       threads=16)
-    PT.check(Tg, Yg, og["counters"], To, Yo, co, c["rtol"], c["atol"], max(2, int(0.15 * 12)))
+    PT.check(Tg, Yg, og["counters"], To, Yo, co, c["rtol"], c["atol"], PT.max_flips("c4p", 12),
+             long_set=True)
 
 
 def test_registers_equal_lds(R):

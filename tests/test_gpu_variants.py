@@ -66,6 +66,6 @@ def test_variant_global_step(R, cfg, G, ask, ran):
     To, Yo, co = O.Model(m).integrate(st["T"], st["P"], st["Y"], c["dt"], c["rtol"], c["atol"],
                                       threads=THREADS)
     assert (out["status"] == 0).all() and (co["status"] == 0).all()
-    flips = max(2, int(0.15 * n)) if cfg == "c4" else max(1, n // 100)
-    rep = PT.check(T, Y, out["counters"], To, Yo, co, c["rtol"], c["atol"], flips)
+    rep = PT.check(T, Y, out["counters"], To, Yo, co, c["rtol"], c["atol"],
+                   PT.max_flips(cfg, n), long_set=cfg in PT.LONG_SETS)
     _say(rep)
