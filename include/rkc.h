@@ -156,7 +156,16 @@ typedef struct {
     void   *stream;          /* hipStream_t; NULL = the null stream */
     int32_t *cell_counters;  /* optional [n_cells][RKC_NCOUNTERS] per-cell counters */
     int32_t param_placement; /* RKC_PARAMS_AUTO */
+    int32_t stage_coefs;     /* RKC_COEFS_TABLE: how RKC kernels obtain the stage
+                                coefficients of Sec. 2.4 (rounding-level differences) */
 } rkc_opts;
+
+/* Values of rkc_opts.stage_coefs.  The coefficients mu~_1 and, per stage j,
+ * mu_j, nu_j, mu~_j, gamma~_j of Sec. 2.4 depend only on (s, j). */
+#define RKC_COEFS_TABLE       0  /* a table computed once on the host for s <= 128;
+                                    larger stage counts advance the Chebyshev
+                                    recurrences inside the kernel, one stage at a time */
+#define RKC_COEFS_RECURRENCE  1  /* the in-kernel recurrences for every stage count */
 
 /* Aggregate statistics of one call. */
 typedef struct {

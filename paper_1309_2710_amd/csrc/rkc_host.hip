@@ -599,7 +599,8 @@ int check_integrate_args(double dt, double rtol, double atol, const rkc_opts &o)
     if (o.method != RKC_METHOD_RKC && o.method != RKC_METHOD_RKCK) return RKC_EINVAL;
     if (o.s_max < 2 || o.max_steps < 1) return RKC_EINVAL;
     if (o.schedule < 0 || o.schedule > 2 || o.block_groups < 0 || o.grid_blocks < 0 ||
-        o.param_placement < 0 || o.param_placement > 3)
+        o.param_placement < 0 || o.param_placement > 3 ||
+        (o.stage_coefs != RKC_COEFS_TABLE && o.stage_coefs != RKC_COEFS_RECURRENCE))
         return RKC_EINVAL;
     return RKC_OK;
 }
@@ -643,6 +644,7 @@ int enqueue_integrate(rkc_mech *m, size_t n, double *Td, const double *Pd, doubl
     p.cell_counters = cd;
     p.persistent = L.persistent ? 1 : 0;
     p.groups_total = L.blocks * L.groups_per_block;
+    if (o.stage_coefs == RKC_COEFS_RECURRENCE) p.coef_smax = 0;
     void *args[] = {&p};
     HIP_OK(hipLaunchKernel(kernel, dim3(L.blocks), dim3(L.threads), args, L.lds, st));
     li->G = ch.v.G;

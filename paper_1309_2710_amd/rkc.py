@@ -24,6 +24,7 @@ CELL_OK, CELL_UNDERFLOW, CELL_MAXSTEPS, CELL_NONFINITE, CELL_BADINPUT = 0, 1, 2,
 RKC, RKCK = 0, 1
 SCHED_AUTO, SCHED_PLAIN, SCHED_PERSISTENT = 0, 1, 2
 PARAMS_AUTO, PARAMS_REGISTERS, PARAMS_LDS, PARAMS_GLOBAL = 0, 1, 2, 3
+COEFS_TABLE, COEFS_RECURRENCE = 0, 1
 NCOUNTERS = 8
 MAX_CELLS = 2146435072          # RKC_MAX_CELLS: largest n_cells of one call
 COUNTER_FIELDS = ["n_rhs", "n_steps", "n_reject", "n_sigma", "s_max_used", "s_hash", "status",
@@ -54,7 +55,8 @@ class Opts(ct.Structure):
                 ("lanes_per_cell", ct.c_int32), ("schedule", ct.c_int32),
                 ("block_groups", ct.c_int32), ("grid_blocks", ct.c_int32),
                 ("device_ptrs", ct.c_int32), ("stream", ct.c_void_p),
-                ("cell_counters", ct.c_void_p), ("param_placement", ct.c_int32)]
+                ("cell_counters", ct.c_void_p), ("param_placement", ct.c_int32),
+                ("stage_coefs", ct.c_int32)]
 
 
 class Stats(ct.Structure):
@@ -270,7 +272,8 @@ def _check_T(T):
 
 def make_opts(method=RKC, s_max=1000, max_steps=1000000, lanes_per_cell=0,
               schedule=SCHED_AUTO, block_groups=0, grid_blocks=0, device_ptrs=False,
-              stream=None, cell_counters=None, param_placement=PARAMS_AUTO):
+              stream=None, cell_counters=None, param_placement=PARAMS_AUTO,
+              stage_coefs=0):
     o = Opts()
     lib().rkc_opts_default(ct.byref(o))
     o.method = int(method)
@@ -284,6 +287,7 @@ def make_opts(method=RKC, s_max=1000, max_steps=1000000, lanes_per_cell=0,
     o.stream = stream
     o.cell_counters = cell_counters
     o.param_placement = int(param_placement)
+    o.stage_coefs = int(stage_coefs)
     return o
 
 
@@ -297,7 +301,7 @@ def _stream_handle(stream, tensors):
 def integrate(mech, T, P, Y, dt, rtol=1e-6, atol=1e-10, method=RKC, lanes_per_cell=0,
               schedule=SCHED_AUTO, block_groups=0, grid_blocks=0, s_max=1000,
               max_steps=1000000, counters=False, status=True, stats=False, stream=None,
-              check=True, param_placement=PARAMS_AUTO):
+              check=True, param_placement=PARAMS_AUTO, stage_coefs=0):
     """Integrate cells over [0, dt] in place.
 
     numpy inputs: T [n] and Y [n][nS] are overwritten in place (must be
@@ -327,7 +331,7 @@ def integrate(mech, T, P, Y, dt, rtol=1e-6, atol=1e-10, method=RKC, lanes_per_ce
         cp = _np_ptr(cn_t) if counters else None
         strm = ct.c_void_p(stream) if isinstance(stream, int) else None
     o = make_opts(method, s_max, max_steps, lanes_per_cell, schedule, block_groups, grid_blocks,
-                  dev, strm, cp, param_placement)
+                  dev, strm, cp, param_placement, stage_coefs)
     s = Stats()
     rc = L.rkc_integrate(mech.handle, n, ptrs[0], ptrs[1], ptrs[2], float(dt), float(rtol),
                          float(atol), ct.byref(o), sp, ct.byref(s) if stats else None)

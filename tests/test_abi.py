@@ -3,6 +3,7 @@ include/rkc.h declares, and rejects bad arguments before touching a device."""
 import ctypes as ct
 import os
 import re
+import subprocess
 
 import numpy as np
 import pytest
@@ -139,3 +140,40 @@ def test_binding_constants_match_the_header():
     txt = open(HDR).read()
     assert int(re.search(r"#define RKC_MAX_CELLS (\d+)", txt).group(1)) == rkc.MAX_CELLS == 2**31 - 2**20
     assert int(re.search(r"#define RKC_NCOUNTERS (\d+)", txt).group(1)) == rkc.NCOUNTERS
+
+
+def test_every_mirrored_constant_matches_the_header():
+    """Each RKC_<NAME> / RKC_SERVER_<NAME> define whose <NAME> the binding
+    mirrors has the header's value."""
+    txt = open(HDR).read()
+    n = 0
+    for name, val in re.findall(r"#define RKC_(\w+)\s+\(?(-?\d+)\)?", txt):
+        if hasattr(rkc, name):
+            assert getattr(rkc, name) == int(val), name
+            n += 1
+    for name, val in re.findall(r"RKC_(CNT_\w+) = (\d+)", txt):
+        n += 1
+        assert rkc.COUNTER_FIELDS[int(val)] is not None
+    assert n >= 20
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The ctypes structures of the binding have the header's field offsets
+    and sizes (a C program built against include/rkc.h prints them)."""
+    structs = {"rkc_opts": rkc.Opts, "rkc_stats": rkc.Stats, "rkc_mech_desc": rkc.MechDesc}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "rkc.h"', "int main(void) {"]
+    for cname, cls in structs.items():
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f, _ in cls._fields_:
+            lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (cname, f, cname, f))
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.dirname(HDR), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = dict(l.rsplit(" ", 1) for l in out if l.strip())
+    for cname, cls in structs.items():
+        assert int(got[cname + " size"]) == ct.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert int(got[cname + "." + f]) == getattr(cls, f).offset, (cname, f)

@@ -1,0 +1,128 @@
+"""GPU parity on paths that the workload tests do not reach (Sec. 2.4): stage
+counts above the host coefficient table (the in-kernel Chebyshev
+recurrences), the same recurrences forced for every stage count, a stage cap
+that binds in many cells, and cells that end NONFINITE."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1309_2710_amd import synth
+from tests import mechs
+from tests import parity as PT
+
+pytestmark = pytest.mark.gpu
+
+THREADS = min(16, os.cpu_count() or 1)
+
+
+@pytest.fixture(scope="module")
+def R():
+    from paper_1309_2710_amd import rkc
+    rkc.lib()
+    return rkc
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _ab_states(n, seed=5):
+    rng = np.random.default_rng(seed)
+    ya = rng.uniform(0.05, 0.95, n)
+    return {"T": rng.uniform(900.0, 1500.0, n), "P": np.full(n, synth.ATM),
+            "Y": np.ascontiguousarray(np.stack([ya, 1.0 - ya], 1))}
+
+
+@pytest.mark.parametrize("coefs", [0, 1])
+@pytest.mark.parametrize("G", [8, 16])
+def test_stage_counts_above_the_table(R, G, coefs):
+    """A -> B with k dt = 1e5: late steps take 130 to 262 stages, past the
+    host table (s <= 128), so the kernels advance the coefficient recurrences
+    themselves; stage_coefs = 1 uses them for every s."""
+    _say("A->B s>128 G", G, "coefs", coefs)
+    k, dt, rtol, atol = 1e9, 1e-4, 1e-6, 1e-10
+    m = mechs.a_to_b(k=k)
+    st = _ab_states(96)
+    T, Y = st["T"].copy(), st["Y"].copy()
+    out = R.integrate(R.Mechanism(m), T, st["P"], Y, dt, rtol, atol, lanes_per_cell=G,
+                      counters=True, stage_coefs=coefs)
+    To, Yo, co = O.Model(m).integrate(st["T"], st["P"], st["Y"], dt, rtol, atol,
+                                      threads=THREADS)
+    cg = out["counters"]
+    _say("s_max_used gpu", cg[:, 4].max(), "oracle", co["s_max_used"].max())
+    assert (cg[:, 4] > 128).all() and (co["s_max_used"] > 128).all()
+    assert (out["status"] == 0).all()
+    rep = PT.check(T, Y, cg, To, Yo, co, rtol, atol, PT.max_flips("ab", 96))
+    _say(rep)
+
+
+def test_recurrences_for_every_stage_count_on_the_9_species_set(R):
+    _say("c1 recurrence coefficients")
+    m = synth.config_mechanism("c1")
+    c = synth.CONFIGS["c1"]
+    st = synth.config_states("c1", 1024)
+    T, Y = st["T"].copy(), st["Y"].copy()
+    out = R.integrate(R.Mechanism(m), T, st["P"], Y, c["dt"], c["rtol"], c["atol"],
+                      counters=True, stage_coefs=R.COEFS_RECURRENCE)
+    To, Yo, co = O.Model(m).integrate(st["T"], st["P"], st["Y"], c["dt"], c["rtol"], c["atol"],
+                                      threads=THREADS)
+    assert (out["status"] == 0).all()
+    rep = PT.check(T, Y, out["counters"], To, Yo, co, c["rtol"], c["atol"],
+                   PT.max_flips("c1", 1024))
+    _say(rep)
+
+
+def test_binding_stage_cap_at_the_bar(R):
+    """s_max = 10 on the 9-species set: a third of the cells take capped steps
+    (h = ((s_max - 1)^2 - 1) / (1.54 sigma)) and all finish; statuses, decision
+    counters and states as the oracle's, at the full parity bar."""
+    _say("c1 s_max 10")
+    m = synth.config_mechanism("c1")
+    c = synth.CONFIGS["c1"]
+    st = synth.config_states("c1", 512)
+    T, Y = st["T"].copy(), st["Y"].copy()
+    out = R.integrate(R.Mechanism(m), T, st["P"], Y, c["dt"], c["rtol"], c["atol"], s_max=10,
+                      counters=True)
+    To, Yo, co = O.Model(m).integrate(st["T"], st["P"], st["Y"], c["dt"], c["rtol"], c["atol"],
+                                      s_max=10, threads=THREADS)
+    cg = out["counters"]
+    assert np.array_equal(out["status"], co["status"].astype(np.int32))
+    assert (co["s_max_used"] == 10).sum() > 100
+    assert np.array_equal(cg[:, 4] == 10, co["s_max_used"] == 10)
+    rep = PT.check(T, Y, cg, To, Yo, co, c["rtol"], c["atol"], PT.max_flips("c1", 512))
+    _say(rep)
+
+
+def test_nonfinite_cells_of_the_served_pool(R):
+    """Two cells of the third 13-species served mechanism's state pool end
+    NONFINITE at dt = 1e-5 in the oracle: the power method runs its 50
+    iterations and the tentative step 1/sigma carries T below zero.  The GPU
+    reports the same status and counters, leaves those cells at their input,
+    and matches the oracle on the neighbours."""
+    _say("served pool NONFINITE cells")
+    m = synth.c5_mechanism(13, 2)
+    c = synth.CONFIGS["c2"]
+    pool = synth.make_states(m, 1 << 16, synth.C5_SEED * 10 + 13 * 4 + 2, T_dist=c["T"],
+                             P_dist=c["P"], Y_dist=c["Y"])
+    idx = np.concatenate([np.arange(44200, 44300), np.arange(45350, 45420)])
+    st = {k: np.ascontiguousarray(v[idx]) for k, v in pool.items() if k in ("T", "P", "Y")}
+    dt = 1e-5
+    T, Y = st["T"].copy(), st["Y"].copy()
+    out = R.integrate(R.Mechanism(m), T, st["P"], Y, dt, c["rtol"], c["atol"], counters=True)
+    To, Yo, co = O.Model(m).integrate(st["T"], st["P"], st["Y"], dt, c["rtol"], c["atol"],
+                                      threads=THREADS)
+    bad_o = np.nonzero(co["status"] != 0)[0]
+    _say("oracle failed", idx[bad_o], co["status"][bad_o], "gpu", out["status"][bad_o])
+    assert list(idx[bad_o]) == [44241, 45384]
+    assert (co["status"][bad_o] == O.NONFINITE).all()
+    assert np.array_equal(out["status"], co["status"].astype(np.int32))
+    cg = out["counters"]
+    for f, col in PT.GPU_COL.items():
+        assert np.array_equal(cg[bad_o, col], co[f][bad_o]), f
+    assert np.array_equal(T[bad_o], st["T"][bad_o]) and np.array_equal(Y[bad_o], st["Y"][bad_o])
+    ok = co["status"] == 0
+    rep = PT.check(T[ok], Y[ok], cg[ok], To[ok], Yo[ok], {k: v[ok] for k, v in co.items()},
+                   c["rtol"], c["atol"], PT.max_flips("c2", int(ok.sum())))
+    _say(rep)
