@@ -89,13 +89,15 @@ def test_closed_forms_on_the_gpu(R):
     assert ratio == pytest.approx(Fc, rel=1e-12)
 
 
-@pytest.mark.parametrize("troe", [[0.5, 1e-30, 1e30, 0.0], [0.3, 1e-30, 1e-30, 1e30],
+@pytest.mark.parametrize("troe", [[0.5, 1e-30, 1e30, 0.0], [0.3, 1e-30, 1e3, 1e30],
                                   [0.7, 1e30, 1e-30, 1e-30]])
 def test_troe_sentinel_temperatures_against_oracle(R, troe):
     """Troe temperatures used as 'term off' sentinels (1e-30 and 1e30 K): the
     centre value's exponentials have arguments far beyond the exponential's
     int32 exponent range (-T/1e-30 is -1e33), where the result is exactly 0
-    or 1; over 800-2400 K the source term must equal the oracle's."""
+    or 1; over 800-2400 K the source term must equal the oracle's.  Each case
+    keeps one term alive: with all three off F_cent is 0 and its logarithm,
+    hence the Troe factor, is undefined (the oracle gives NaN)."""
     _say("troe sentinels", troe)
     kinf, k0 = 2.0e5, 4.0e10
     m = _pdep(mechs.a_to_b(kinf, 10.0), [3], k0=[k0], troe=[troe])

@@ -91,3 +91,41 @@ def test_a_floor_at_atol_is_out_of_reach(variants):
     worst = max(_measure("c1", 512, L)["max_rel_err_matching_floor_atol"]
                 for L in variants.values())
     assert worst > 1e3 * PT.TOL
+
+
+def test_long_horizon_stiff_case_flips_decisions_between_roundings():
+    """The stiff A -> B case of the GPU stage-count tests (k dt = 1e5, about
+    700 steps of up to 363 stages per cell): the oracle rebuilt with mu_j of
+    Sec. 2.4 formed with the reciprocal of b_{j-1} takes a different step
+    sequence in a sizeable fraction of the cells, while every cell still ends
+    within 1e-8 of the unchanged oracle.  This is why that case is held to
+    the 1e-8 bar in every cell but not to equal decision counters."""
+    from tests import mechs
+    src = open(oracle_build.SRC).read()
+    a = "mu[j] = 2.0 * b[j] * w0 / b[j - 1];"
+    assert src.count(a) == 1
+    tmp = tempfile.mkdtemp(prefix="orc_mu_")
+    try:
+        path = os.path.join(tmp, "mu.c")
+        with open(path, "w") as fh:
+            fh.write(src.replace(a, "mu[j] = 2.0 * b[j] * w0 * (1.0 / b[j - 1]);"))
+        lib = os.path.join(tmp, "libmu.so")
+        subprocess.run(["gcc", "-std=c99", "-O2", "-ffp-contract=off", "-fno-fast-math",
+                        "-fPIC", "-shared", "-pthread", "-w", "-o", lib, path, "-lm"], check=True)
+        L = O.load_variant(lib)
+        m = mechs.a_to_b(k=1e9)
+        rng = np.random.default_rng(5)
+        ya = rng.uniform(0.05, 0.95, 96)
+        st = (rng.uniform(900.0, 1500.0, 96), np.full(96, synth.ATM),
+              np.ascontiguousarray(np.stack([ya, 1.0 - ya], 1)))
+        args = st + (1e-4, 1e-6, 1e-10)
+        To, Yo, co = O.Model(m).integrate(*args, threads=THREADS)
+        T1, Y1, c1 = O.Model(m, library=L).integrate(*args, threads=THREADS)
+    finally:
+        shutil.rmtree(tmp, ignore_errors=True)
+    cg = np.stack([c1[f] for f in O.COUNTER_FIELDS], 1)
+    rep = PT.report(T1, Y1, cg, To, Yo, co, 1e-10)
+    print("[rounding] A->B k dt 1e5", rep, "steps", co["n_steps"].mean(), flush=True)
+    assert co["n_steps"].mean() > 500 and co["s_max_used"].max() > 300
+    assert rep["n_counter_mismatch"] >= 10
+    assert rep["max_rel_err"] <= PT.TOL / 2
