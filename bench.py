@@ -117,6 +117,10 @@ def main():
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--schedule", type=int, default=0)
     ap.add_argument("--params", type=int, default=0, help="0 auto, 1 registers, 2 LDS, 3 global memory")
+    ap.add_argument("--layout", type=int, default=None,
+                    help="memory order of Y: 0 cell-major Y[cell][species], 1 species-major "
+                         "(cell-fastest) Y[species][cell]; default: species-major for one lane "
+                         "per cell, else cell-major")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--autotune", action="store_true",
                     help="choose schedule and workgroup size with rkc_autotune on a strided "
@@ -169,18 +173,20 @@ def main():
     n = st["T"].shape[0]
     dev = torch.device("cuda:0")
     gm = rkc.Mechanism(mech)
+    layout = args.layout if args.layout is not None else (1 if args.lanes == 1 else 0)
     T0 = torch.from_numpy(st["T"]).to(dev)
     P = torch.from_numpy(st["P"]).to(dev)
-    Y0 = torch.from_numpy(st["Y"]).to(dev)
+    Y0 = torch.from_numpy(st["Y"] if layout == 0 else np.ascontiguousarray(st["Y"].T)).to(dev)
     T = T0.clone()
     Y = Y0.clone()
     kw = dict(lanes_per_cell=args.lanes, schedule=args.schedule, status=False,
-              param_placement=args.params)
+              param_placement=args.params, layout=layout)
     tuned = None
     if args.autotune:
         idx = torch.arange(0, n, max(1, n // 16384), device=dev)[:16384]
+        Ys = Y0[idx] if layout == 0 else Y0[:, idx].t()
         tuned, tuned_ms = rkc.autotune(gm, T0[idx].contiguous(), P[idx].contiguous(),
-                                       Y0[idx].contiguous(), c["dt"], c["rtol"], c["atol"],
+                                       Ys.contiguous(), c["dt"], c["rtol"], c["atol"],
                                        lanes_per_cell=args.lanes, param_placement=args.params)
         kw.update(schedule=tuned["schedule"], block_groups=tuned["block_groups"])
 
@@ -205,7 +211,7 @@ def main():
     if args.graph:
         graph = rkc.Graph(gm, T, P, Y, c["dt"], c["rtol"], c["atol"], lanes_per_cell=args.lanes,
                           schedule=kw["schedule"], block_groups=kw.get("block_groups", 0),
-                          param_placement=args.params)
+                          param_placement=args.params, layout=layout)
 
     # Timed region: K consecutive global steps, device-resident state.
     stream = torch.cuda.current_stream(dev)
@@ -277,6 +283,7 @@ def main():
                    "n_species": mech["n_species"], "n_reactions": mech["n_reactions"],
                    "dt": c["dt"], "rtol": c["rtol"], "atol": c["atol"],
                    "lanes_per_cell": census[0]["lanes_per_cell"],
+                   "layout": ["cell-major", "species-major"][layout],
                    "schedule": ["auto", "plain", "persistent"][census[0]["schedule"]],
                    "launch": "hip graph replay" if graph is not None else "rkc_integrate",
                    "autotuned": tuned,

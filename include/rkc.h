@@ -145,10 +145,17 @@ typedef struct {
     int32_t method;          /* RKC_METHOD_RKC */
     int32_t s_max;           /* 1000: largest RKC stage count (>= 2) */
     int32_t max_steps;       /* 1000000: accepted + rejected steps per cell */
-    int32_t lanes_per_cell;  /* 0 = automatic; else 8, 16, 32 or 64.  Automatic:
+    int32_t lanes_per_cell;  /* 0 = automatic; else 1, 8, 16, 32 or 64.  Automatic:
                                 N = n_species + 1 state elements, 16 lanes for
                                 N <= 16, 32 for N <= 39 (or N <= 64 with
-                                pressure-dependent reactions), else 64 */
+                                pressure-dependent reactions), else 64.
+                                1 = one lane per cell (N <= 32): each lane of a
+                                wavefront integrates its own cell, the mechanism
+                                tables are read as wave-uniform scalars, and a
+                                wave's per-cell rows of concentrations and net
+                                production rates ((2 n_species + 2 + efficiency
+                                sets) x 512 bytes) must fit in LDS, else
+                                RKC_ENOTSUP */
     int32_t schedule;        /* RKC_SCHED_AUTO */
     int32_t block_groups;    /* lane groups per workgroup, 0 = automatic */
     int32_t grid_blocks;     /* persistent grid size in workgroups, 0 = automatic */
@@ -158,7 +165,20 @@ typedef struct {
     int32_t param_placement; /* RKC_PARAMS_AUTO */
     int32_t stage_coefs;     /* RKC_COEFS_TABLE: how RKC kernels obtain the stage
                                 coefficients of Sec. 2.4 (rounding-level differences) */
+    int32_t layout;          /* RKC_LAYOUT_CELL_MAJOR: memory order of Y (and of f
+                                in rkc_rhs) */
 } rkc_opts;
+
+/* Values of rkc_opts.layout (the same for host and device arrays; T and P are
+ * always [n_cells]):
+ *   CELL_MAJOR     Y[cell][species] (element i of cell c at Y[c * n_species + i]),
+ *                  f[cell][k] (at f[c * (n_species + 1) + k])
+ *   SPECIES_MAJOR  Y[species][cell] (at Y[i * n_cells + c]), f[k][cell] (at
+ *                  f[k * n_cells + c]): cell-fastest, so the lanes of a wave
+ *                  that each hold one cell (lanes_per_cell = 1) read and write
+ *                  consecutive doubles */
+#define RKC_LAYOUT_CELL_MAJOR     0
+#define RKC_LAYOUT_SPECIES_MAJOR  1
 
 /* Values of rkc_opts.stage_coefs.  The coefficients mu~_1 and, per stage j,
  * mu_j, nu_j, mu~_j, gamma~_j of Sec. 2.4 depend only on (s, j). */

@@ -111,6 +111,18 @@ struct Params {
     int *queue;                      // persistent work-queue head
     int persistent;
     int groups_total;                // groups in the launched grid
+    // element (cell, i) of Y is Y[cell * ycs + i * yss] and element (cell, k)
+    // of F is F[cell * fcs + k * fss]: (n_species, 1) and (N, 1) for
+    // cell-major arrays, (1, n_cells) for species-major (cell-fastest) ones
+    long long ycs, yss, fcs, fss;
+    // one-lane-per-cell kernels (rkc_lane.h): wave-uniform tables read with
+    // scalar loads, and the LDS rows of one wave
+    const double *l_spec;            // [nS][LS_FIELDS] species records
+    const double *l_units;           // [nU][LU_DOUBLES] unit records with their terms
+    const double *l_pdep;            // [units past n_plain][PDEP_DOUBLES], unit order
+    const double *l_eff;             // [NMS][nS] third-body efficiencies
+    int n_plain;                     // units [0, n_plain) have no pressure dependence
+    int lane_rows;                   // LDS rows of 64 doubles per wave
 };
 
 // RKC stage coefficients (E:rkc1, E:rkcj) depend on the stage count s and
@@ -905,7 +917,7 @@ __global__ __launch_bounds__((Occ<RUC, NSL>::threads), (Occ<RUC, NSL>::waves)) v
         double v = 0.0;
         if (active) {
             if (k == 0) v = p.T[cell];
-            else if (k < p.N) v = p.Y[(size_t)cell * p.nS + (k - 1)];
+            else if (k < p.N) v = p.Y[(long long)cell * p.ycs + (long long)(k - 1) * p.yss];
         }
         z[s] = v;
     }
@@ -917,7 +929,7 @@ __global__ __launch_bounds__((Occ<RUC, NSL>::threads), (Occ<RUC, NSL>::waves)) v
 #pragma unroll
         for (int s = 0; s < NSL; ++s) {
             const int k = s * G + g;
-            if (k < p.N) p.F[(size_t)cell * p.N + k] = fz[s];
+            if (k < p.N) p.F[(long long)cell * p.fcs + (long long)k * p.fss] = fz[s];
         }
     }
 }

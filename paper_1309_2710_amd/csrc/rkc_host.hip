@@ -10,6 +10,7 @@
 
 #include "rkc.h"
 #include "rkc_internal.h"
+#include "rkc_lane.h"
 
 using rkcdev::NFIELD;
 using rkcdev::UNIT_DOUBLES;
@@ -63,6 +64,10 @@ struct rkc_mech {
     size_t stage_bytes = 0;
     int num_cus = 0;
     size_t max_lds = 0;
+    // tables of the one-lane-per-cell kernels (built on first use)
+    double *l_spec_d = nullptr;        // [nS][LS_FIELDS]
+    double *l_units_d = nullptr;       // [nU][LU_DOUBLES]
+    double *l_eff_d = nullptr;         // [NMS][nS]
 };
 
 namespace {
@@ -389,6 +394,82 @@ int ensure_tables(rkc_mech *m, int G, int NK, int RU, NkTables **out) {
     return RKC_OK;
 }
 
+// Tables of the one-lane-per-cell kernels (rkc_lane.h): species records of
+// LS_FIELDS doubles (W, 1/W, T_mid, the Horner coefficients of Cp/R and H/(RT)
+// per range), and unit records of LU_DOUBLES doubles: the lane-group record
+// followed by the unit's net-production terms (LDS rows of the species'
+// production rates in 16-bit fields, unused slots naming the discard row,
+// then nu'' - nu' of each as a double, 0 for unused slots), in species order.
+int ensure_lane_tables(rkc_mech *m) {
+    if (m->l_spec_d) return RKC_OK;
+    const int nS = m->nS, nU = m->nU;
+    std::vector<double> spec((size_t)nS * rkcdev::LS_FIELDS, 0.0);
+    for (int i = 0; i < nS; ++i) {
+        double *r = &spec[(size_t)i * rkcdev::LS_FIELDS];
+        r[rkcdev::LS_W] = m->W[i];
+        r[rkcdev::LS_INVW] = 1.0 / m->W[i];
+        r[rkcdev::LS_TMID] = m->Tmid[i];
+        const double *a[2] = {&m->lo[7 * i], &m->hi[7 * i]};
+        const int cpo[2] = {rkcdev::LS_CPLO, rkcdev::LS_CPHI};
+        const int ho[2] = {rkcdev::LS_HLO, rkcdev::LS_HHI};
+        for (int q = 0; q < 2; ++q) {
+            for (int c = 0; c < 5; ++c) r[cpo[q] + c] = a[q][c];
+            r[ho[q] + 0] = a[q][0];
+            r[ho[q] + 1] = a[q][1] / 2.0;
+            r[ho[q] + 2] = a[q][2] / 3.0;
+            r[ho[q] + 3] = a[q][3] / 4.0;
+            r[ho[q] + 4] = a[q][4] / 5.0;
+            r[ho[q] + 5] = a[q][5];
+        }
+    }
+    // terms of each unit, in species order
+    std::vector<std::vector<std::pair<int, int>>> terms(nU);
+    for (int i = 0; i < nS; ++i)
+        for (const auto &pr : m->rows[i]) terms[pr.first].push_back({i, pr.second});
+    std::vector<double> units((size_t)std::max(1, nU) * rkcdev::LU_DOUBLES, 0.0);
+    for (int u = 0; u < nU; ++u) {
+        if ((int)terms[u].size() > rkcdev::LU_TERMS) return RKC_ENOTSUP;   // cannot happen: <= 6 species
+        double *r = &units[(size_t)u * rkcdev::LU_DOUBLES];
+        std::memcpy(r, &m->units_h[(size_t)u * UNIT_DOUBLES], UNIT_DOUBLES * sizeof(double));
+        uint64_t w[2] = {0, 0};
+        for (int t = 0; t < rkcdev::LU_TERMS; ++t) {
+            const bool used = t < (int)terms[u].size();
+            const uint64_t row = used ? (uint64_t)(rkcdev::lane_row_omega(nS) + terms[u][t].first)
+                                      : (uint64_t)rkcdev::lane_row_discard(nS);
+            w[t / 4] |= row << (16 * (t % 4));
+            r[10 + t] = used ? (double)terms[u][t].second : 0.0;
+        }
+        std::memcpy(&r[8], &w[0], 8);
+        std::memcpy(&r[9], &w[1], 8);
+    }
+    const int NMS = (int)m->effsets.size();
+    std::vector<double> eff((size_t)std::max(1, NMS) * nS, 0.0);
+    for (int q = 0; q < NMS; ++q)
+        for (int i = 0; i < nS; ++i) eff[(size_t)q * nS + i] = m->effsets[q][i];
+    double *sp = nullptr, *ef = nullptr, *un = nullptr;
+    if (hipMalloc(&sp, spec.size() * 8) != hipSuccess || hipMalloc(&ef, eff.size() * 8) != hipSuccess ||
+        hipMalloc(&un, units.size() * 8) != hipSuccess) {
+        (void)hipFree(sp); (void)hipFree(ef); (void)hipFree(un);
+        return RKC_ENOMEM;
+    }
+    if (hipMemcpy(sp, spec.data(), spec.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(ef, eff.data(), eff.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(un, units.data(), units.size() * 8, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(sp); (void)hipFree(ef); (void)hipFree(un);
+        return RKC_EDEVICE;
+    }
+    m->l_spec_d = sp;
+    m->l_eff_d = ef;
+    m->l_units_d = un;
+    return RKC_OK;
+}
+
+// LDS rows of 64 doubles one wave of a one-lane-per-cell kernel needs:
+// concentrations, net production rates, third-body concentrations.
+int lane_rows(const rkc_mech *m) {
+    return rkcdev::lane_row_mset(m->nS) + (m->n_pdep > 0 ? (int)m->effsets.size() : 0);
+}
+
 struct Choice {
     rkchost::VariantDesc v;
     int RU;
@@ -417,6 +498,18 @@ const rkchost::VariantDesc *find_variant(int G, int NSL, int RUC) {
 // two-slot kernels (53-species falloff set: 3.23 M against 2.79 M cell-ODEs/s
 // at 64 lanes; without pressure-dependent units the two are level).
 int choose_variant(const rkc_mech *m, int lanes, int placement, Choice *out) {
+    if (lanes == 1) {
+        // one lane per cell: the smallest state capacity that holds N
+        int n = 0;
+        const rkchost::VariantDesc *tab = rkchost::variants_lane(&n);
+        const rkchost::VariantDesc *pick = nullptr;
+        for (int i = 0; i < n; ++i)
+            if (tab[i].NSL >= m->N && (!pick || tab[i].NSL < pick->NSL)) pick = &tab[i];
+        if (!pick) return RKC_ENOTSUP;
+        out->v = *pick;
+        out->RU = m->nU;
+        return RKC_OK;
+    }
     int G = lanes;
     if (G == 0) {
         G = (m->N >= 40) ? 64 : (m->N > 16 ? 32 : 16);
@@ -463,6 +556,10 @@ rkcdev::Shape shape_for(const Choice &ch, const NkTables *nk) {
 int select_variant(rkc_mech *m, const rkc_opts &o, Choice *ch, NkTables **nk) {
     int rc = choose_variant(m, o.lanes_per_cell, o.param_placement, ch);
     if (rc) return rc;
+    if (ch->v.G == 1) {
+        *nk = nullptr;
+        return ensure_lane_tables(m);
+    }
     rc = ensure_tables(m, ch->v.G, ch->v.NSL * ch->v.G, ch->RU, nk);
     if (rc) return rc;
     if (ch->v.RUC != 0 || o.param_placement == RKC_PARAMS_LDS) return RKC_OK;
@@ -500,7 +597,50 @@ struct Launch {
 };
 
 int plan_launch(const rkc_mech *m, const Choice &ch, const void *kernel, size_t n_cells,
+                const rkc_opts &o, bool allow_persistent, NkTables *nk, Launch *L);
+
+// One lane per cell: workgroups of up to 256 lanes (o.block_groups lanes,
+// rounded up to whole waves), fewer waves when their LDS rows do not fit.
+int plan_lane_launch(const rkc_mech *m, const Choice &ch, const void *kernel, size_t n_cells,
+                     const rkc_opts &o, bool allow_persistent, Launch *L) {
+    const size_t wave_bytes = (size_t)lane_rows(m) * rkcdev::LROW;
+    int waves = o.block_groups > 0 ? (o.block_groups + 63) / 64 : 4;
+    waves = std::min(waves, ch.v.max_threads / 64);
+    while (waves > 1 && wave_bytes * (size_t)waves > m->max_lds) --waves;
+    if (waves < 1 || wave_bytes * (size_t)waves > m->max_lds) return RKC_ENOTSUP;
+    L->groups_per_block = waves * 64;
+    L->threads = waves * 64;
+    L->lds = wave_bytes * (size_t)waves;
+    hipFuncAttributes fa{};
+    HIP_OK(hipFuncGetAttributes(&fa, kernel));
+    if (L->threads > fa.maxThreadsPerBlock) return RKC_ENOTSUP;
+    if (hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L->lds) !=
+        hipSuccess)
+        return RKC_EDEVICE;
+    const size_t blocks_all = (n_cells + L->threads - 1) / L->threads;
+    L->persistent = false;
+    size_t blocks = blocks_all;
+    if (allow_persistent && o.schedule != RKC_SCHED_PLAIN) {
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, L->threads, L->lds) !=
+            hipSuccess)
+            return RKC_EDEVICE;
+        per_cu = std::max(1, per_cu);
+        size_t resident = (size_t)per_cu * (size_t)m->num_cus;
+        if (o.grid_blocks > 0) resident = (size_t)o.grid_blocks;
+        if (o.schedule == RKC_SCHED_PERSISTENT || resident < blocks_all) {
+            L->persistent = true;
+            blocks = std::min(blocks_all, resident);
+        }
+    }
+    if (blocks > 0x7fffffff) return RKC_ENOTSUP;
+    L->blocks = (int)std::max<size_t>(1, blocks);
+    return RKC_OK;
+}
+
+int plan_launch(const rkc_mech *m, const Choice &ch, const void *kernel, size_t n_cells,
                 const rkc_opts &o, bool allow_persistent, NkTables *nk, Launch *L) {
+    if (ch.v.G == 1) return plan_lane_launch(m, ch, kernel, n_cells, o, allow_persistent, L);
     const int G = ch.v.G;
     const int NK = nk->NK;
     const int max_threads = ch.v.max_threads;
@@ -546,6 +686,28 @@ void fill_params(const rkc_mech *m, const Choice &ch, const NkTables *nk, rkcdev
     std::memset(p, 0, sizeof(*p));
     p->nS = m->nS;
     p->N = m->N;
+    p->ycs = m->nS;
+    p->yss = 1;
+    p->fcs = m->N;
+    p->fss = 1;
+    if (ch.v.G == 1) {
+        p->nU = m->nU;
+        p->RU = m->nU;
+        p->NMS = (int)m->effsets.size();
+        p->n_plain = m->n_plain;
+        p->tab.units = m->units_d;
+        p->l_spec = m->l_spec_d;
+        p->l_units = m->l_units_d;
+        p->l_pdep = m->pdep_d;
+        p->l_eff = m->l_eff_d;
+        p->lane_rows = lane_rows(m);
+        p->agg = m->agg_d;
+        p->queue = m->queue_d;
+        p->coef = m->coef_d;
+        p->coef_smax = m->coef_d ? COEF_SMAX : 0;
+        p->invN = 1.0 / (double)m->N;
+        return;
+    }
     p->NK = nk->NK;
     p->nU = m->nU;
     p->RU = ch.RU;
@@ -600,7 +762,8 @@ int check_integrate_args(double dt, double rtol, double atol, const rkc_opts &o)
     if (o.s_max < 2 || o.max_steps < 1) return RKC_EINVAL;
     if (o.schedule < 0 || o.schedule > 2 || o.block_groups < 0 || o.grid_blocks < 0 ||
         o.param_placement < 0 || o.param_placement > 3 ||
-        (o.stage_coefs != RKC_COEFS_TABLE && o.stage_coefs != RKC_COEFS_RECURRENCE))
+        (o.stage_coefs != RKC_COEFS_TABLE && o.stage_coefs != RKC_COEFS_RECURRENCE) ||
+        (o.layout != RKC_LAYOUT_CELL_MAJOR && o.layout != RKC_LAYOUT_SPECIES_MAJOR))
         return RKC_EINVAL;
     return RKC_OK;
 }
@@ -645,6 +808,10 @@ int enqueue_integrate(rkc_mech *m, size_t n, double *Td, const double *Pd, doubl
     p.persistent = L.persistent ? 1 : 0;
     p.groups_total = L.blocks * L.groups_per_block;
     if (o.stage_coefs == RKC_COEFS_RECURRENCE) p.coef_smax = 0;
+    if (o.layout == RKC_LAYOUT_SPECIES_MAJOR) {
+        p.ycs = 1;
+        p.yss = (long long)n;
+    }
     void *args[] = {&p};
     HIP_OK(hipLaunchKernel(kernel, dim3(L.blocks), dim3(L.threads), args, L.lds, st));
     li->G = ch.v.G;
@@ -739,6 +906,9 @@ int rkc_mech_destroy(rkc_mech *m) {
     if (m->coef_d) (void)hipFree(m->coef_d);
     if (m->pdep_d) (void)hipFree(m->pdep_d);
     if (m->stage_d) (void)hipFree(m->stage_d);
+    if (m->l_spec_d) (void)hipFree(m->l_spec_d);
+    if (m->l_units_d) (void)hipFree(m->l_units_d);
+    if (m->l_eff_d) (void)hipFree(m->l_eff_d);
     (void)hipSetDevice(dev);
     delete m;
     return RKC_OK;
@@ -1009,6 +1179,14 @@ int rkc_rhs(const rkc_mech *mc, size_t n, const double *T, const double *P, cons
     p.P = Pd;
     p.Y = const_cast<double *>(Yd);
     p.F = fd;
+    if (o.layout == RKC_LAYOUT_SPECIES_MAJOR) {
+        p.ycs = 1;
+        p.yss = (long long)n;
+        p.fcs = 1;
+        p.fss = (long long)n;
+    } else if (o.layout != RKC_LAYOUT_CELL_MAJOR) {
+        return RKC_EINVAL;
+    }
     void *args[] = {&p};
     HIP_OK(hipLaunchKernel(krhs, dim3(L.blocks), dim3(L.threads), args, L.lds, st));
     if (!o.device_ptrs) {

@@ -101,7 +101,7 @@ __device__ __forceinline__ bool load_state(const Params &p, int cell, int g, dou
             v = p.T[cell];
             bad |= !(v > 0.0) || !isfinite(v);
         } else if (k < p.N) {
-            v = p.Y[(size_t)cell * p.nS + (k - 1)];
+            v = p.Y[(long long)cell * p.ycs + (long long)(k - 1) * p.yss];
             bad |= !isfinite(v);
         }
         y[s] = v;
@@ -119,7 +119,7 @@ __device__ __forceinline__ void store_state(const Params &p, int cell, int g, co
     for (int s = 0; s < NSL; ++s) {
         const int k = s * G + g;
         if (k == 0) p.T[cell] = y[s];
-        else if (k < p.N) p.Y[(size_t)cell * p.nS + (k - 1)] = y[s];
+        else if (k < p.N) p.Y[(long long)cell * p.ycs + (long long)(k - 1) * p.yss] = y[s];
     }
 }
 

@@ -27,6 +27,8 @@ const VariantDesc *variants_g64(int *n);
 const VariantDesc *variants_g32(int *n);
 const VariantDesc *variants_g16(int *n);
 const VariantDesc *variants_g8(int *n);
+// one lane per cell (G = 1, NSL = the state capacity NMAX of the kernel)
+const VariantDesc *variants_lane(int *n);
 
 // Aggregate counters per launch (n_rhs, n_steps, n_reject, n_sigma,
 // n_power_iter, s_max_used, n_failed, worst_status, issued slots; rest spare).

@@ -181,7 +181,7 @@ int rkc_server_create(const rkc_server_opts *opts, rkc_server **out) {
     if (o.n_streams < 1 || o.n_streams > 16 || o.budget_bytes < ((size_t)1 << 20) ||
         o.max_batch_cells < 1 || o.param_placement < 0 || o.param_placement > 3)
         return RKC_EINVAL;
-    if (o.lanes_per_cell != 0 && o.lanes_per_cell != 8 && o.lanes_per_cell != 16 &&
+    if (o.lanes_per_cell != 0 && o.lanes_per_cell != 1 && o.lanes_per_cell != 8 && o.lanes_per_cell != 16 &&
         o.lanes_per_cell != 32 && o.lanes_per_cell != 64)
         return RKC_EINVAL;
     rkc_server *s = new (std::nothrow) rkc_server();

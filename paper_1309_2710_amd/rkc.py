@@ -25,6 +25,7 @@ RKC, RKCK = 0, 1
 SCHED_AUTO, SCHED_PLAIN, SCHED_PERSISTENT = 0, 1, 2
 PARAMS_AUTO, PARAMS_REGISTERS, PARAMS_LDS, PARAMS_GLOBAL = 0, 1, 2, 3
 COEFS_TABLE, COEFS_RECURRENCE = 0, 1
+LAYOUT_CELL_MAJOR, LAYOUT_SPECIES_MAJOR = 0, 1
 NCOUNTERS = 8
 MAX_CELLS = 2146435072          # RKC_MAX_CELLS: largest n_cells of one call
 COUNTER_FIELDS = ["n_rhs", "n_steps", "n_reject", "n_sigma", "s_max_used", "s_hash", "status",
@@ -56,7 +57,7 @@ class Opts(ct.Structure):
                 ("block_groups", ct.c_int32), ("grid_blocks", ct.c_int32),
                 ("device_ptrs", ct.c_int32), ("stream", ct.c_void_p),
                 ("cell_counters", ct.c_void_p), ("param_placement", ct.c_int32),
-                ("stage_coefs", ct.c_int32)]
+                ("stage_coefs", ct.c_int32), ("layout", ct.c_int32)]
 
 
 class Stats(ct.Structure):
@@ -233,10 +234,12 @@ def _is_torch(x):
     return type(x).__module__.startswith("torch")
 
 
-def _check_shapes(mech, n, P, Y):
+def _check_shapes(mech, n, P, Y, layout=LAYOUT_CELL_MAJOR):
     """The C ABI takes bare pointers: check here that P is [n] and Y is
-    [n][n_species] of this mechanism."""
-    if tuple(P.shape) != (n,) or tuple(Y.shape) != (n, mech.n_species):
+    [n][n_species] of this mechanism ([n_species][n] for the species-major
+    layout)."""
+    want = (n, mech.n_species) if layout == LAYOUT_CELL_MAJOR else (mech.n_species, n)
+    if tuple(P.shape) != (n,) or tuple(Y.shape) != want:
         raise ValueError("shape mismatch: T [%d], P %s, Y %s for a mechanism with %d species"
                          % (n, tuple(P.shape), tuple(Y.shape), mech.n_species))
 
@@ -273,7 +276,7 @@ def _check_T(T):
 def make_opts(method=RKC, s_max=1000, max_steps=1000000, lanes_per_cell=0,
               schedule=SCHED_AUTO, block_groups=0, grid_blocks=0, device_ptrs=False,
               stream=None, cell_counters=None, param_placement=PARAMS_AUTO,
-              stage_coefs=0):
+              stage_coefs=0, layout=LAYOUT_CELL_MAJOR):
     o = Opts()
     lib().rkc_opts_default(ct.byref(o))
     o.method = int(method)
@@ -288,6 +291,7 @@ def make_opts(method=RKC, s_max=1000, max_steps=1000000, lanes_per_cell=0,
     o.cell_counters = cell_counters
     o.param_placement = int(param_placement)
     o.stage_coefs = int(stage_coefs)
+    o.layout = int(layout)
     return o
 
 
@@ -301,19 +305,20 @@ def _stream_handle(stream, tensors):
 def integrate(mech, T, P, Y, dt, rtol=1e-6, atol=1e-10, method=RKC, lanes_per_cell=0,
               schedule=SCHED_AUTO, block_groups=0, grid_blocks=0, s_max=1000,
               max_steps=1000000, counters=False, status=True, stats=False, stream=None,
-              check=True, param_placement=PARAMS_AUTO, stage_coefs=0):
+              check=True, param_placement=PARAMS_AUTO, stage_coefs=0,
+              layout=LAYOUT_CELL_MAJOR):
     """Integrate cells over [0, dt] in place.
 
-    numpy inputs: T [n] and Y [n][nS] are overwritten in place (must be
-    C-contiguous float64).  torch GPU inputs: the same, on the device.
-    Returns dict with optional 'status' [n] int32, 'counters' [n][8] int32,
-    'stats' (dict), 'rc'.
+    numpy inputs: T [n] and Y [n][nS] ([nS][n] with layout=LAYOUT_SPECIES_MAJOR)
+    are overwritten in place (must be C-contiguous float64).  torch GPU
+    inputs: the same, on the device.  Returns dict with optional 'status' [n]
+    int32, 'counters' [n][8] int32, 'stats' (dict), 'rc'.
     """
     L = lib()
     dev = _check_arrays([T, P, Y])
     _check_T(T)
     n = int(T.shape[0])
-    _check_shapes(mech, n, P, Y)
+    _check_shapes(mech, n, P, Y, layout)
     out = {}
     if dev:
         import torch
@@ -331,7 +336,7 @@ def integrate(mech, T, P, Y, dt, rtol=1e-6, atol=1e-10, method=RKC, lanes_per_ce
         cp = _np_ptr(cn_t) if counters else None
         strm = ct.c_void_p(stream) if isinstance(stream, int) else None
     o = make_opts(method, s_max, max_steps, lanes_per_cell, schedule, block_groups, grid_blocks,
-                  dev, strm, cp, param_placement, stage_coefs)
+                  dev, strm, cp, param_placement, stage_coefs, layout)
     s = Stats()
     rc = L.rkc_integrate(mech.handle, n, ptrs[0], ptrs[1], ptrs[2], float(dt), float(rtol),
                          float(atol), ct.byref(o), sp, ct.byref(s) if stats else None)
@@ -376,16 +381,17 @@ class Graph:
 
     def __init__(self, mech, T, P, Y, dt, rtol=1e-6, atol=1e-10, method=RKC, lanes_per_cell=0,
                  schedule=SCHED_AUTO, block_groups=0, grid_blocks=0, s_max=1000,
-                 max_steps=1000000, status=None, param_placement=PARAMS_AUTO):
+                 max_steps=1000000, status=None, param_placement=PARAMS_AUTO,
+                 layout=LAYOUT_CELL_MAJOR):
         if not _check_arrays([T, P, Y]):
             raise TypeError("a graph records device arrays: torch GPU tensors expected")
         _check_T(T)
-        _check_shapes(mech, int(T.shape[0]), P, Y)
+        _check_shapes(mech, int(T.shape[0]), P, Y, layout)
         if status is not None and (not _check_arrays([status], int32=True)
                                    or tuple(status.shape) != (int(T.shape[0]),)):
             raise ValueError("status must be an int32 GPU tensor [n_cells]")
         o = make_opts(method, s_max, max_steps, lanes_per_cell, schedule, block_groups,
-                      grid_blocks, True, None, None, param_placement)
+                      grid_blocks, True, None, None, param_placement, layout=layout)
         h = ct.c_void_p()
         rc = lib().rkc_graph_create(mech.handle, int(T.shape[0]), ct.c_void_p(T.data_ptr()),
                                     ct.c_void_p(P.data_ptr()), ct.c_void_p(Y.data_ptr()),
@@ -442,26 +448,28 @@ def divergence(work, width=32, stride=1, stream=None):
     return D
 
 
-def rhs(mech, T, P, Y, lanes_per_cell=0, stream=None):
-    """Source term f [n][nS+1] (column 0 = dT/dt) for numpy or torch GPU inputs."""
+def rhs(mech, T, P, Y, lanes_per_cell=0, stream=None, layout=LAYOUT_CELL_MAJOR):
+    """Source term f [n][nS+1] (column 0 = dT/dt) for numpy or torch GPU inputs
+    (Y [nS][n] and f [nS+1][n] with layout=LAYOUT_SPECIES_MAJOR)."""
     L = lib()
     _check_T(T)
     n = int(T.shape[0])
-    _check_shapes(mech, n, P, Y)
+    _check_shapes(mech, n, P, Y, layout)
     N = mech.n_species + 1
+    fshape = (n, N) if layout == LAYOUT_CELL_MAJOR else (N, n)
     if _is_torch(T):
         import torch
         _check_arrays([T, P, Y])
-        f = torch.empty((n, N), dtype=torch.float64, device=T.device)
+        f = torch.empty(fshape, dtype=torch.float64, device=T.device)
         ptrs = [ct.c_void_p(a.data_ptr()) for a in (T, P, Y, f)]
         o = make_opts(lanes_per_cell=lanes_per_cell, device_ptrs=True,
-                      stream=_stream_handle(stream, [T]))
+                      stream=_stream_handle(stream, [T]), layout=layout)
     else:
-        f = np.empty((n, N), np.float64)
+        f = np.empty(fshape, np.float64)
         # host inputs are copied by the call: any float array is converted first
         keep = [np.ascontiguousarray(a, np.float64) for a in (T, P, Y)]
         ptrs = [_np_ptr(a) for a in keep] + [_np_ptr(f)]
-        o = make_opts(lanes_per_cell=lanes_per_cell)
+        o = make_opts(lanes_per_cell=lanes_per_cell, layout=layout)
     rc = L.rkc_rhs(mech.handle, n, *ptrs, ct.byref(o))
     if rc != OK:
         raise RkcError(rc, "rkc_rhs")
