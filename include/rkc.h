@@ -252,6 +252,27 @@ int rkc_integrate(const rkc_mech *mech, size_t n_cells, double *T, const double 
                   double *Y, double dt, double rtol, double atol, const rkc_opts *opts,
                   int32_t *cell_status, rkc_stats *stats);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation):
+ * rkc_integrate with device arrays (opts->device_ptrs must be 1, opts must not
+ * be NULL) that calls no hipMalloc, hipFree or other allocating routine.  The
+ * launch's scratch -- the aggregate counters and the work-queue head of the
+ * kernels, 256 bytes -- is a file-scope device array of the library, one per
+ * GPU, cleared by a kernel at the start of every call; the call's size limit is
+ * that of rkc_integrate (RKC_MAX_CELLS cells, RKC_ENOTSUP above).  Results are
+ * those of rkc_integrate with the same options.  The mechanism's tables for the
+ * kernel variant these options select are built by the first ordinary call
+ * (rkc_integrate, rkc_rhs or rkc_graph_create with the same lanes_per_cell and
+ * param_placement); before that this call returns RKC_ENOTSUP and does
+ * nothing.  The work is enqueued on opts->stream and the call returns without
+ * waiting; statistics are not available (use rkc_integrate for them).  Calls
+ * on one GPU share its scratch: calls that overlap in time on one GPU race
+ * (the same rule as calls sharing a mechanism handle).  Errors: RKC_EINVAL
+ * (host arrays, NULL, bad scalars), RKC_ENOTSUP, RKC_EDEVICE. */
+int rkc_integrate_device_noalloc(const rkc_mech *mech, size_t n_cells, double *T,
+                                 const double *P, double *Y, double dt, double rtol,
+                                 double atol, const rkc_opts *opts, int32_t *cell_status);
+
 /* Choose the launch grain for a workload by timing it: runs rkc_integrate
  * over the given cells (left unchanged: the runs use internal copies) with
  * each candidate setting of the options that never change results --

@@ -306,9 +306,10 @@ int plan_gather(const rkc_mech *m, int G, int NK, int RU, GatherPlan *gp) {
     return RKC_OK;
 }
 
-int ensure_tables(rkc_mech *m, int G, int NK, int RU, NkTables **out) {
+int ensure_tables(rkc_mech *m, int G, int NK, int RU, NkTables **out, bool may_build = true) {
     for (auto &t : m->nk)
         if (t.NK == NK && t.G == G) { *out = &t; return RKC_OK; }
+    if (!may_build) return RKC_ENOTSUP;
     const int nS = m->nS;
     std::vector<double> spec((size_t)NFIELD * NK, 0.0);
     for (int i = 0; i < nS; ++i) {
@@ -400,8 +401,9 @@ int ensure_tables(rkc_mech *m, int G, int NK, int RU, NkTables **out) {
 // followed by the unit's net-production terms (LDS rows of the species'
 // production rates in 16-bit fields, unused slots naming the discard row,
 // then nu'' - nu' of each as a double, 0 for unused slots), in species order.
-int ensure_lane_tables(rkc_mech *m) {
+int ensure_lane_tables(rkc_mech *m, bool may_build = true) {
     if (m->l_spec_d) return RKC_OK;
+    if (!may_build) return RKC_ENOTSUP;
     const int nS = m->nS, nU = m->nU;
     std::vector<double> spec((size_t)nS * rkcdev::LS_FIELDS, 0.0);
     for (int i = 0; i < nS; ++i) {
@@ -553,14 +555,15 @@ rkcdev::Shape shape_for(const Choice &ch, const NkTables *nk) {
 // reaction parameters: automatic placement keeps them in LDS unless LDS then
 // limits the workgroup below the variant's occupancy target and a variant
 // reading them from global memory exists for the same shape.
-int select_variant(rkc_mech *m, const rkc_opts &o, Choice *ch, NkTables **nk) {
+int select_variant(rkc_mech *m, const rkc_opts &o, Choice *ch, NkTables **nk,
+                   bool may_build = true) {
     int rc = choose_variant(m, o.lanes_per_cell, o.param_placement, ch);
     if (rc) return rc;
     if (ch->v.G == 1) {
         *nk = nullptr;
-        return ensure_lane_tables(m);
+        return ensure_lane_tables(m, may_build);
     }
-    rc = ensure_tables(m, ch->v.G, ch->v.NSL * ch->v.G, ch->RU, nk);
+    rc = ensure_tables(m, ch->v.G, ch->v.NSL * ch->v.G, ch->RU, nk, may_build);
     if (rc) return rc;
     if (ch->v.RUC != 0 || o.param_placement == RKC_PARAMS_LDS) return RKC_OK;
     const rkchost::VariantDesc *glob = find_variant(ch->v.G, ch->v.NSL, -1);
@@ -770,10 +773,11 @@ int check_integrate_args(double dt, double rtol, double atol, const rkc_opts &o)
 
 int enqueue_integrate(rkc_mech *m, size_t n, double *Td, const double *Pd, double *Yd, double dt,
                       double rtol, double atol, const rkc_opts &o, int32_t *sd, int32_t *cd,
-                      unsigned long long *agg_d, int *queue_d, hipStream_t st, LaunchInfo *li) {
+                      unsigned long long *agg_d, int *queue_d, hipStream_t st, LaunchInfo *li,
+                      bool may_build) {
     Choice ch;
     NkTables *nk = nullptr;
-    int rc = select_variant(m, o, &ch, &nk);
+    int rc = select_variant(m, o, &ch, &nk, may_build);
     if (rc) return rc;
     const bool pd = m->n_pdep > 0;
     const void *kernel = o.method == RKC_METHOD_RKC ? (pd ? ch.v.k_rkc_pd : ch.v.k_rkc)

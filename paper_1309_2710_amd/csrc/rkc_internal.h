@@ -53,10 +53,13 @@ int check_integrate_args(double dt, double rtol, double atol, const rkc_opts &o)
 // mechanism's device, with the launch's own scratch (aggregate counters
 // [16], work-queue head): launches that use distinct scratch may run
 // concurrently on different streams.  Not thread-safe for one mechanism
-// (its per-shape table cache is filled on first use).
+// (its per-shape table cache is filled on first use).  With may_build false
+// nothing is allocated: RKC_ENOTSUP if the tables of the selected variant
+// have not been built by an earlier call.
 int enqueue_integrate(rkc_mech *m, size_t n, double *Td, const double *Pd, double *Yd, double dt,
                       double rtol, double atol, const rkc_opts &o, int32_t *sd, int32_t *cd,
-                      unsigned long long *agg_d, int *queue_d, hipStream_t st, LaunchInfo *li);
+                      unsigned long long *agg_d, int *queue_d, hipStream_t st, LaunchInfo *li,
+                      bool may_build = true);
 
 // Select the variant and build the device tables a later enqueue_integrate
 // with these options will use (so that concurrent launches only read them);

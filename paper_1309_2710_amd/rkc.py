@@ -32,8 +32,9 @@ COUNTER_FIELDS = ["n_rhs", "n_steps", "n_reject", "n_sigma", "s_max_used", "s_ha
                   "n_power_iter"]
 
 EXPORTED = ["rkc_opts_default", "rkc_mech_create", "rkc_mech_destroy", "rkc_mech_info",
-            "rkc_rhs", "rkc_integrate", "rkc_autotune", "rkc_divergence", "rkc_graph_create",
-            "rkc_graph_launch", "rkc_graph_destroy", "rkc_strerror"]
+            "rkc_rhs", "rkc_integrate", "rkc_integrate_device_noalloc", "rkc_autotune",
+            "rkc_divergence", "rkc_graph_create", "rkc_graph_launch", "rkc_graph_destroy",
+            "rkc_strerror"]
 SERVER_EXPORTED = ["rkc_server_opts_default", "rkc_server_create", "rkc_server_destroy",
                    "rkc_server_register_mech", "rkc_server_submit", "rkc_server_poll",
                    "rkc_server_wait", "rkc_server_get_stats", "rkc_server_reset_stats"]
@@ -123,6 +124,10 @@ def lib():
         L.rkc_integrate.argtypes = [ct.c_void_p, ct.c_size_t, ct.c_void_p, ct.c_void_p,
                                     ct.c_void_p, ct.c_double, ct.c_double, ct.c_double,
                                     ct.POINTER(Opts), ct.c_void_p, ct.POINTER(Stats)]
+        L.rkc_integrate_device_noalloc.argtypes = [ct.c_void_p, ct.c_size_t, ct.c_void_p,
+                                                   ct.c_void_p, ct.c_void_p, ct.c_double,
+                                                   ct.c_double, ct.c_double, ct.POINTER(Opts),
+                                                   ct.c_void_p]
         L.rkc_divergence.argtypes = [ct.c_size_t, ct.c_void_p, ct.c_int32, ct.c_int32,
                                      ct.c_void_p, ct.POINTER(Opts)]
         L.rkc_autotune.argtypes = [ct.c_void_p, ct.c_size_t, ct.c_void_p, ct.c_void_p,
@@ -350,6 +355,36 @@ def integrate(mech, T, P, Y, dt, rtol=1e-6, atol=1e-10, method=RKC, lanes_per_ce
     if stats:
         out["stats"] = s.as_dict()
     return out
+
+
+def integrate_noalloc(mech, T, P, Y, dt, rtol=1e-6, atol=1e-10, method=RKC, lanes_per_cell=0,
+                      schedule=SCHED_AUTO, block_groups=0, grid_blocks=0, s_max=1000,
+                      max_steps=1000000, status=None, counters=None, stream=None,
+                      param_placement=PARAMS_AUTO, stage_coefs=0, layout=LAYOUT_CELL_MAJOR,
+                      check=True):
+    """rkc_integrate_device_noalloc on torch GPU tensors, in place: no device
+    memory is allocated by the library (status [n] and counters [n][8] int32
+    tensors are optional outputs the caller owns).  Returns the C return code
+    (raises on an error unless check is False)."""
+    if not _check_arrays([T, P, Y]):
+        raise TypeError("device arrays expected: torch GPU tensors")
+    _check_T(T)
+    n = int(T.shape[0])
+    _check_shapes(mech, n, P, Y, layout)
+    for a, shape in ((status, (n,)), (counters, (n, NCOUNTERS))):
+        if a is not None and (not _check_arrays([a], int32=True) or tuple(a.shape) != shape):
+            raise ValueError("status must be int32 [n_cells], counters int32 [n_cells][8]")
+    o = make_opts(method, s_max, max_steps, lanes_per_cell, schedule, block_groups, grid_blocks,
+                  True, _stream_handle(stream, [T]),
+                  ct.c_void_p(counters.data_ptr()) if counters is not None else None,
+                  param_placement, stage_coefs, layout)
+    rc = lib().rkc_integrate_device_noalloc(
+        mech.handle, n, ct.c_void_p(T.data_ptr()), ct.c_void_p(P.data_ptr()),
+        ct.c_void_p(Y.data_ptr()), float(dt), float(rtol), float(atol), ct.byref(o),
+        ct.c_void_p(status.data_ptr()) if status is not None else None)
+    if check and rc != OK:
+        raise RkcError(rc, "rkc_integrate_device_noalloc")
+    return rc
 
 
 def autotune(mech, T, P, Y, dt, rtol=1e-6, atol=1e-10, method=RKC, lanes_per_cell=0,

@@ -1,0 +1,99 @@
+"""The allocation-free entry point (rkc_integrate_device_noalloc) against
+rkc_integrate with the same options: bitwise equal states, statuses and
+per-cell counters, on two calls in a row (the second smaller), for the
+lane-group and the one-lane-per-cell kernels and both methods; refusal before
+the tables exist, for host arrays and above the size limit."""
+import ctypes as ct
+
+import numpy as np
+import pytest
+
+from paper_1309_2710_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def R():
+    from paper_1309_2710_amd import rkc
+    rkc.lib()
+    return rkc
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _dev(st, n, layout=0):
+    import torch
+    d = torch.device("cuda:0")
+    Y = st["Y"][:n] if layout == 0 else np.ascontiguousarray(st["Y"][:n].T)
+    return (torch.from_numpy(np.ascontiguousarray(st["T"][:n])).to(d),
+            torch.from_numpy(np.ascontiguousarray(st["P"][:n])).to(d),
+            torch.from_numpy(np.ascontiguousarray(Y)).to(d))
+
+
+CASES = [("c1", 0, 0, 0), ("c2", 16, 0, 0), ("c2", 1, 1, 0), ("c1", 16, 0, 1)]
+
+
+@pytest.mark.parametrize("cfg,lanes,layout,method", CASES)
+def test_noalloc_matches_integrate(R, cfg, lanes, layout, method):
+    import torch
+    _say("noalloc", cfg, "lanes", lanes, "layout", layout, "method", method)
+    c = synth.CONFIGS[cfg]
+    dt, rtol = (1e-8, 1e-10) if method == 1 else (c["dt"], c["rtol"])
+    gm = R.Mechanism(synth.config_mechanism(cfg))
+    kw = dict(method=method, lanes_per_cell=lanes, layout=layout)
+    st1 = synth.config_states(cfg, 3000, seed=401)
+    st2 = synth.config_states(cfg, 700, seed=402)
+
+    # before any ordinary call the tables of the variant do not exist: refused
+    T, P, Y = _dev(st1, 3000, layout)
+    T0, Y0 = T.clone(), Y.clone()
+    rc = R.integrate_noalloc(gm, T, P, Y, dt, rtol, c["atol"], check=False, **kw)
+    torch.cuda.synchronize()
+    assert rc == R.ENOTSUP
+    assert torch.equal(T, T0) and torch.equal(Y, Y0)
+
+    for st, n in ((st1, 3000), (st2, 700)):   # two calls in a row, the second smaller
+        Ta, Pa, Ya = _dev(st, n, layout)
+        ref = R.integrate(gm, Ta, Pa, Ya, dt, rtol, c["atol"], counters=True, **kw)
+        Tb, Pb, Yb = _dev(st, n, layout)
+        sb = torch.full((n,), -7, dtype=torch.int32, device=Tb.device)
+        cb = torch.full((n, R.NCOUNTERS), -7, dtype=torch.int32, device=Tb.device)
+        R.integrate_noalloc(gm, Tb, Pb, Yb, dt, rtol, c["atol"], status=sb, counters=cb, **kw)
+        torch.cuda.synchronize()
+        assert torch.equal(Ta, Tb) and torch.equal(Ya, Yb)
+        assert torch.equal(ref["status"], sb) and torch.equal(ref["counters"], cb)
+        assert int((sb == 0).sum()) == n
+        _say("n", n, "equal; rhs", int(cb[:, 0].sum()))
+
+
+def test_noalloc_refusals(R):
+    import torch
+    _say("noalloc refusals")
+    c = synth.CONFIGS["c1"]
+    gm = R.Mechanism(synth.config_mechanism("c1"))
+    st = synth.config_states("c1", 64)
+    T, P, Y = _dev(st, 64)
+    R.integrate(gm, T.clone(), P, Y.clone(), c["dt"])   # builds the default tables
+    L = R.lib()
+    # host arrays
+    Th, Ph, Yh = st["T"].copy(), st["P"].copy(), st["Y"].copy()
+    o = R.make_opts()
+    rc = L.rkc_integrate_device_noalloc(gm.handle, 64, R._np_ptr(Th), R._np_ptr(Ph),
+                                        R._np_ptr(Yh), c["dt"], 1e-6, 1e-10, ct.byref(o), None)
+    assert rc == R.EINVAL
+    # NULL options, bad scalars, more cells than one call takes
+    T0, Y0 = T.clone(), Y.clone()
+    od = R.make_opts(device_ptrs=True)
+    args = (ct.c_void_p(T.data_ptr()), ct.c_void_p(P.data_ptr()), ct.c_void_p(Y.data_ptr()))
+    assert L.rkc_integrate_device_noalloc(gm.handle, 64, *args, c["dt"], 1e-6, 1e-10, None,
+                                          None) == R.EINVAL
+    assert L.rkc_integrate_device_noalloc(gm.handle, 64, *args, -1.0, 1e-6, 1e-10,
+                                          ct.byref(od), None) == R.EINVAL
+    assert L.rkc_integrate_device_noalloc(gm.handle, R.MAX_CELLS + 1, *args, c["dt"], 1e-6,
+                                          1e-10, ct.byref(od), None) == R.ENOTSUP
+    # nothing was enqueued by the refused calls
+    torch.cuda.synchronize()
+    assert torch.equal(T, T0) and torch.equal(Y, Y0)
