@@ -140,6 +140,10 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-streams", type=int, default=4)
+    ap.add_argument("--served-requests", type=int, default=120,
+                    help="requests of the short served trace in the default line (0: none)")
+    ap.add_argument("--served-util", type=float, default=0.7,
+                    help="offered utilisation of that trace: arrival rate over measured capacity")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one device copy kernel of this many MiB (read + write) after the "
                          "timed region: the known-size reference for HBM byte counters")
@@ -185,10 +189,20 @@ def main():
     if args.autotune:
         idx = torch.arange(0, n, max(1, n // 16384), device=dev)[:16384]
         Ys = Y0[idx] if layout == 0 else Y0[:, idx].t()
+        t_tune = time.perf_counter()
         tuned, tuned_ms = rkc.autotune(gm, T0[idx].contiguous(), P[idx].contiguous(),
                                        Ys.contiguous(), c["dt"], c["rtol"], c["atol"],
                                        lanes_per_cell=args.lanes, param_placement=args.params)
-        kw.update(schedule=tuned["schedule"], block_groups=tuned["block_groups"])
+        tuned["tuning_s"] = time.perf_counter() - t_tune
+        tuned["sample_cells"] = int(idx.shape[0])
+        if tuned["lanes_per_cell"] != kw["lanes_per_cell"] and layout == 1 and \
+                tuned["lanes_per_cell"] != 1:
+            layout = 0   # lane groups read cell-major rows
+            Y0 = torch.from_numpy(st["Y"]).to(dev)
+            Y = Y0.clone()
+            kw["layout"] = 0
+        kw.update(schedule=tuned["schedule"], block_groups=tuned["block_groups"],
+                  lanes_per_cell=tuned["lanes_per_cell"], param_placement=tuned["param_placement"])
 
     # Warm-up and work census: the K timed steps are replayed once untimed with
     # statistics (results are bitwise deterministic, so the timed run performs
@@ -209,9 +223,10 @@ def main():
 
     graph = None
     if args.graph:
-        graph = rkc.Graph(gm, T, P, Y, c["dt"], c["rtol"], c["atol"], lanes_per_cell=args.lanes,
-                          schedule=kw["schedule"], block_groups=kw.get("block_groups", 0),
-                          param_placement=args.params, layout=layout)
+        graph = rkc.Graph(gm, T, P, Y, c["dt"], c["rtol"], c["atol"],
+                          lanes_per_cell=kw["lanes_per_cell"], schedule=kw["schedule"],
+                          block_groups=kw.get("block_groups", 0),
+                          param_placement=kw["param_placement"], layout=layout)
 
     # Timed region: K consecutive global steps, device-resident state.
     stream = torch.cuda.current_stream(dev)
@@ -292,6 +307,7 @@ def main():
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
                      "traffic": measured_traffic(workload_tag(mech, n))},
         "pcie_inclusive": pcie,
+        "fp64_probe": fp64_probe(),
         "work": {"rhs_evals_per_step": tot_rhs / args.steps, "flops_per_rhs": f_rhs,
                  "flops_per_stage_update": f_stage,
                  "mean_rhs_per_cell": tot_rhs / args.steps / n,
@@ -300,9 +316,32 @@ def main():
                  "rhs_utilisation": tot_rhs / max(1, sum(s["n_rhs_slots"] for s in census)),
                  "s_max_used": max(s["s_max_used"] for s in census)},
     }
+    if args.served_requests > 0 and args.config == "c3" and not args.graph:
+        del T, Y, T0, Y0, P
+        out["served"] = served_block(args.served_requests, args.served_util)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(mech, c, st, args.steps, args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def fp64_probe():
+    """Measured FP64 vector FMA throughput of the GPU (the probe library:
+    independent FMA chains, 4 waves per SIMD), beside the published peak the
+    roofline uses."""
+    import ctypes as ct
+
+    from paper_1309_2710_amd import build as lib_build
+
+    L = ct.CDLL(lib_build.PROBE_LIB)
+    L.rkc_probe_fp64_fma.argtypes = [ct.c_int, ct.c_int, ct.POINTER(ct.c_double),
+                                     ct.POINTER(ct.c_float)]
+    f, ms = ct.c_double(), ct.c_float()
+    rc = L.rkc_probe_fp64_fma(4 * 256, 100000, ct.byref(f), ct.byref(ms))
+    if rc != 0:
+        return {"error": rc}
+    return {"tflops": f.value / 1e12, "of_published_peak": f.value / 1e12 / PEAK_FP64_TFLOPS,
+            "ms": ms.value, "kernel": "1024 workgroups x 256 lanes, 16 independent FMA chains "
+                                      "per lane, 100000 steps"}
 
 
 def trajectory_states(rkc, gm, c, synth, mech, n_traj, n_samp, seed):
@@ -332,7 +371,7 @@ def trajectory_states(rkc, gm, c, synth, mech, n_traj, n_samp, seed):
 
 
 def study_divergence(args):
-    """Throughput and divergence D (Sec. 3.2) for ignition-sampled states in
+    """Throughput and divergence D (Sec. 3.1) for ignition-sampled states in
     trajectory order and shuffled, plain and persistent schedules, on the
     13-species (16 lanes per cell: 4 cells per wavefront) and the 53-species
     (64 lanes: one cell per wavefront) sets."""
@@ -424,6 +463,99 @@ def study_crossover(args):
     out = {"metric": "RKC vs RKCK crossover in the global step", "unit": "cell-ODEs/s",
            "n_gpus": 1, "dtype": "f64", "data": "synthetic", "rows": rows}
     print(json.dumps(out), flush=True)
+
+
+def served_block(n_requests, util):
+    """Batch latency of the served workload at a stated offered utilisation.
+
+    The mixed 13/53-species request stream (1024-65536 cells, dt 1e-6 or
+    1e-5 s, fresh compositions) is first served back to back with
+    rkc_integrate to measure the GPU's capacity for it (requests per second
+    = requests / total service time); the same requests are then replayed with
+    Poisson arrivals at util x capacity through the integration server, and
+    through sequential rkc_integrate calls as the baseline.  Latency runs from
+    arrival to completion, so at util < 1 p50/p99 measure service plus the
+    queueing of a stable system."""
+    import threading
+
+    from paper_1309_2710_amd import rkc, synth
+
+    trace = synth.c5_trace(n_requests=n_requests, rate=1.0)   # arrival times rescaled below
+    keys = sorted({r["mech"] for r in trace})
+    mechs = {k: synth.c5_mechanism(*k) for k in keys}
+    gms = {k: rkc.Mechanism(m) for k, m in mechs.items()}
+    cfg = {13: synth.CONFIGS["c2"], 53: synth.CONFIGS["c3"]}
+    for k in keys:   # first-use tables outside the measurements
+        c = cfg[k[0]]
+        st = synth.make_states(mechs[k], 1, 1, T_dist=c["T"], P_dist=c["P"], Y_dist=c["Y"])
+        rkc.integrate(gms[k], st["T"], st["P"], st["Y"], 1e-6)
+
+    # capacity: the requests back to back
+    inp = serve_inputs(trace, synth)
+    busy = []
+    for r, x in zip(trace, inp):
+        c = cfg[r["mech"][0]]
+        a = time.perf_counter()
+        rkc.integrate(gms[r["mech"]], x["T"], x["P"], x["Y"], r["dt"], c["rtol"], c["atol"])
+        busy.append(time.perf_counter() - a)
+    capacity = len(trace) / sum(busy)
+    rate = util * capacity
+    scale = 1.0 / rate   # the trace was drawn at 1 request/s
+    arrivals = [r["t_arrival"] * scale for r in trace]
+    print("served: capacity %.2f req/s, replay at %.2f req/s" % (capacity, rate),
+          file=sys.stderr, flush=True)
+
+    def pct(v, q):
+        v = sorted(v)
+        return v[min(len(v), max(1, int(np.ceil(q * len(v))))) - 1]
+
+    # sequential baseline at the same arrivals
+    inp = serve_inputs(trace, synth)
+    lat_b = []
+    t0 = time.perf_counter()
+    for r, x, ta in zip(trace, inp, arrivals):
+        now = time.perf_counter() - t0
+        if now < ta:
+            time.sleep(ta - now)
+        c = cfg[r["mech"][0]]
+        rkc.integrate(gms[r["mech"]], x["T"], x["P"], x["Y"], r["dt"], c["rtol"], c["atol"])
+        lat_b.append((time.perf_counter() - t0 - ta) * 1e3)
+
+    # the server
+    inp = serve_inputs(trace, synth)
+    srv = rkc.Server(budget_bytes=4 << 30, n_streams=4)
+    ids = {k: srv.register(m) for k, m in mechs.items()}
+    rids = [None] * len(trace)
+
+    def waiter():
+        for i in range(len(trace)):
+            while rids[i] is None:
+                time.sleep(1e-4)
+            srv.wait(rids[i])
+
+    th = threading.Thread(target=waiter)
+    srv.reset_stats()
+    t0 = time.perf_counter()
+    th.start()
+    for i, (r, x, ta) in enumerate(zip(trace, inp, arrivals)):
+        now = time.perf_counter() - t0
+        if now < ta:
+            time.sleep(ta - now)
+        c = cfg[r["mech"][0]]
+        rids[i] = srv.submit(ids[r["mech"]], x["T"], x["P"], x["Y"], r["dt"], c["rtol"], c["atol"])
+    th.join()
+    wall = time.perf_counter() - t0
+    sst = srv.stats()
+    srv.close()
+    cells = sum(r["n_cells"] for r in trace)
+    return {"p50_ms": sst["p50_ms"], "p99_ms": sst["p99_ms"], "mean_ms": sst["mean_ms"],
+            "offered_utilisation": util, "capacity_req_per_s": capacity,
+            "arrival_rate_req_per_s": rate, "requests": len(trace), "cells": cells,
+            "served_cells_per_s": cells / wall, "failed_requests": sst["failed_requests"],
+            "sequential_p50_ms": pct(lat_b, 0.5), "sequential_p99_ms": pct(lat_b, 0.99),
+            "workload": "mixed 13/53-species requests (4 seeded mechanisms each), "
+                        "2^U(10,16) cells, dt 1e-6 or 1e-5 s, fresh compositions, Poisson "
+                        "arrivals at the stated fraction of the measured capacity"}
 
 
 def serve_inputs(trace, synth):
@@ -578,7 +710,21 @@ def cpu_baseline(mech, c, st, steps, budget_s):
     from oracle import oracle as O
 
     M = O.Model(mech)
-    threads = min(os.cpu_count() or 1, 16)
+    # the host cores this process may use (affinity), within the 16-core
+    # share the GPU host gives one GPU's job
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    threads = max(1, min(usable, 16))
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     n = st["T"].shape[0]
 
     def run(idx):
@@ -605,6 +751,7 @@ def cpu_baseline(mech, c, st, steps, budget_s):
     idx = np.arange(0, n, max(1, n // m))[:m]
     t = run(idx)
     return {"value": len(idx) * steps / t, "unit": "cell-ODEs/s", "cores": threads,
+            "nproc": os.cpu_count(), "usable_cores": usable, "cpu_model": model,
             "kind": "oracle", "one_core_value": one_core,
             "sample": "%d of %d cells (stride %d), %d consecutive global steps, %.1f s"
                       % (len(idx), n, max(1, n // m), steps, t)}

@@ -273,15 +273,23 @@ int rkc_integrate_device_noalloc(const rkc_mech *mech, size_t n_cells, double *T
                                  const double *P, double *Y, double dt, double rtol,
                                  double atol, const rkc_opts *opts, int32_t *cell_status);
 
-/* Choose the launch grain for a workload by timing it: runs rkc_integrate
- * over the given cells (left unchanged: the runs use internal copies) with
- * each candidate setting of the options that never change results --
- * schedule (persistent, plain) and lane groups per workgroup (the largest,
- * half and a quarter) -- and writes *opts with the fastest into *tuned (every
- * other field copied from *opts).  *best_ms (may be NULL) receives its time.
- * A sample of the real cells is the intended input.  Arrays are host or
- * device pointers per opts->device_ptrs; opts may be NULL (defaults).
- * Errors: RKC_EINVAL, RKC_ENOTSUP, RKC_ENOMEM, RKC_EDEVICE. */
+/* Choose the kernel form and launch grain for a workload by timing it: runs
+ * rkc_integrate over the given cells (left unchanged: the runs use internal
+ * copies), each candidate twice after an untimed first run, keeping the
+ * minimum.  Stage 1 times every lanes_per_cell the mechanism can run (1, 8, 16,
+ * 32, 64; or the one requested in *opts) with every parameter placement that
+ * has a compiled variant (or the one requested), persistent schedule; stage 2
+ * times the two fastest with both schedules and workgroups of the largest, half
+ * and a quarter of their lane groups (lanes for one lane per cell).  The fastest
+ * setting is written into *tuned (lanes_per_cell, param_placement, schedule,
+ * block_groups; every other field copied from *opts) and *best_ms (may be NULL)
+ * receives its time.  Schedule, grain and placement never change results;
+ * lanes_per_cell changes them by rounding only (summation order).  The choice
+ * is cached in the mechanism handle by (method, requested lanes_per_cell and
+ * param_placement, layout, floor(log2 n_cells)): a later call with the same key
+ * returns it without timing.  A sample of the real cells is the intended input.
+ * Arrays are host or device pointers per opts->device_ptrs; opts may be NULL
+ * (defaults).  Errors: RKC_EINVAL, RKC_ENOTSUP, RKC_ENOMEM, RKC_EDEVICE. */
 int rkc_autotune(const rkc_mech *mech, size_t n_cells, const double *T, const double *P,
                  const double *Y, double dt, double rtol, double atol, const rkc_opts *opts,
                  rkc_opts *tuned, float *best_ms);
@@ -306,7 +314,7 @@ int rkc_graph_launch(rkc_graph *graph, void *stream);
 /* Release a graph; NULL is accepted. */
 int rkc_graph_destroy(rkc_graph *graph);
 
-/* Divergence measure D of Sec. 3.2 (results section, divergence of GPU
+/* Divergence measure D of Sec. 3.1 (results section, divergence of GPU
  * threads), for runs of `width` consecutive cells:
  *   D_r = (sum_{i in run r} d_i) / (c_r * max_{i in run r} d_i),
  * d_i = work[i * stride] >= 0 the work of cell i (the paper uses its number of

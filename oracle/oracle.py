@@ -207,7 +207,7 @@ def rkc_coeffs(s):
 
 
 def divergence(d, width=32):
-    """Divergence measure D of Sec. 3.2 for consecutive runs of `width` cells:
+    """Divergence measure D of Sec. 3.1 for consecutive runs of `width` cells:
     the run's total work over (run length x its largest work); 1 for a run
     whose work is all zero.  Plain loops over the definition."""
     d = [int(x) for x in d]

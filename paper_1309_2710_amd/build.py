@@ -16,6 +16,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librkc.so")
+PROBE_SRC = os.path.join(CSRC, "probe", "fp64_peak.hip")
+PROBE_LIB = os.path.join(HERE, "librkc_probe.so")
 ARCH = os.environ.get("RKC_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -57,13 +59,20 @@ def build(verbose=False, jobs=None):
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
+    # the FP64 throughput probe of the roofline (bench.py --peak), its own library
+    tmp = PROBE_LIB + ".tmp"
+    cmd = [HIPCC, *CFLAGS, "-shared", PROBE_SRC, "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, PROBE_LIB)
     return LIB
 
 
 def ensure_built():
     """Build the library only if none is built (the tests, the smoke check and
     the benchmark load what is there; build() always recompiles)."""
-    if not os.path.exists(LIB):
+    if not os.path.exists(LIB) or not os.path.exists(PROBE_LIB):
         print("librkc.so not found: building it for %s" % ARCH, flush=True)
         build()
     return LIB

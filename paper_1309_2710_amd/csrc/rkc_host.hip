@@ -68,6 +68,14 @@ struct rkc_mech {
     double *l_spec_d = nullptr;        // [nS][LS_FIELDS]
     double *l_units_d = nullptr;       // [nU][LU_DOUBLES]
     double *l_eff_d = nullptr;         // [NMS][nS]
+    // rkc_autotune results by (method, requested lanes and placement, layout,
+    // log2 of the cell count)
+    struct Tuned {
+        int method, lanes, placement, layout, log2n;
+        rkc_opts opts;
+        float ms;
+    };
+    std::vector<Tuned> tuned;
 };
 
 namespace {
@@ -735,7 +743,7 @@ void fill_params(const rkc_mech *m, const Choice &ch, const NkTables *nk, rkcdev
     p->invN = 1.0 / (double)m->N;
 }
 
-// Divergence measure of a run of consecutive cells (Sec. 3.2): the work of the
+// Divergence measure of a run of consecutive cells (Sec. 3.1): the work of the
 // run over `width` times its largest member's work.
 __global__ void divergence_kernel(const int32_t *w, int stride, long long n, int width,
                                   double *D) {
@@ -1386,12 +1394,22 @@ int rkc_autotune(const rkc_mech *mc, size_t n, const double *T, const double *P,
     if (rc) return rc;
     if (n == 0 || !T || !P || !Y) return RKC_EINVAL;
     if (n > RKC_MAX_CELLS) return RKC_ENOTSUP;
+    int log2n = 0;
+    while (((size_t)1 << (log2n + 1)) <= n) ++log2n;
+    for (const auto &e : m->tuned)
+        if (e.method == o.method && e.lanes == o.lanes_per_cell &&
+            e.placement == o.param_placement && e.layout == o.layout && e.log2n == log2n) {
+            *tuned = o;
+            tuned->lanes_per_cell = e.opts.lanes_per_cell;
+            tuned->param_placement = e.opts.param_placement;
+            tuned->schedule = e.opts.schedule;
+            tuned->block_groups = e.opts.block_groups;
+            tuned->grid_blocks = 0;
+            if (best_ms) *best_ms = e.ms;
+            return RKC_OK;
+        }
     DeviceScope dev;
     HIP_OK(dev.enter(m->device));
-    Choice ch;
-    rc = choose_variant(m, o.lanes_per_cell, o.param_placement, &ch);
-    if (rc) return rc;
-    const int gmax = std::max(1, ch.v.max_threads / ch.v.G);
     hipStream_t st = (hipStream_t)o.stream;
     const size_t nS = (size_t)m->nS;
     // working copies: [T0 | P | Y0 | T | Y | status]
@@ -1409,47 +1427,93 @@ int rkc_autotune(const rkc_mech *mc, size_t n, const double *T, const double *P,
         hip_failed(hipEventCreate(&e0), "event", __LINE__) ||
         hip_failed(hipEventCreate(&e1), "event", __LINE__))
         rc = RKC_EDEVICE;
-    // candidates: both schedules, workgroups of gmax, gmax/2 and gmax/4 groups
-    std::vector<rkc_opts> cand;
-    for (int sched : {RKC_SCHED_PERSISTENT, RKC_SCHED_PLAIN})
-        for (int div : {1, 2, 4}) {
-            if (div > 1 && gmax / div < 1) continue;
+
+    // Time one candidate: `reps` runs from the same copied state (the first
+    // use of a variant, which builds its tables, is not timed); the minimum.
+    auto time_it = [&](const rkc_opts &c, int reps, float *ms_out) -> int {
+        float best = -1.0f;
+        for (int r = -1; r < reps; ++r) {
+            rkchost::LaunchInfo li;
+            if (hip_failed(hipMemcpyAsync(Tw, T0, 8 * n, hipMemcpyDeviceToDevice, st), "copy",
+                           __LINE__) ||
+                hip_failed(hipMemcpyAsync(Yw, Y0, 8 * n * nS, hipMemcpyDeviceToDevice, st), "copy",
+                           __LINE__) ||
+                hip_failed(hipEventRecord(e0, st), "record", __LINE__))
+                return RKC_EDEVICE;
+            const int erc = rkchost::enqueue_integrate(m, n, Tw, Pd, Yw, dt, rtol, atol, c, sd,
+                                                       nullptr, m->agg_d, m->queue_d, st, &li);
+            if (erc) return erc;
+            float ms = 0.0f;
+            if (hip_failed(hipEventRecord(e1, st), "record", __LINE__) ||
+                hip_failed(hipEventSynchronize(e1), "sync", __LINE__) ||
+                hip_failed(hipEventElapsedTime(&ms, e0, e1), "elapsed", __LINE__))
+                return RKC_EDEVICE;
+            if (r >= 0 && (best < 0.0f || ms < best)) best = ms;
+        }
+        *ms_out = best;
+        return RKC_OK;
+    };
+
+    // Stage 1: every lane-group size and parameter placement the mechanism can
+    // run (or the requested ones), default schedule and grain.
+    std::vector<int> lanes_c, place_c;
+    if (o.lanes_per_cell != 0) lanes_c = {o.lanes_per_cell};
+    else lanes_c = {64, 32, 16, 8, 1};
+    if (o.param_placement != RKC_PARAMS_AUTO) place_c = {o.param_placement};
+    else place_c = {RKC_PARAMS_LDS, RKC_PARAMS_GLOBAL, RKC_PARAMS_REGISTERS};
+    struct Cand {
+        rkc_opts c;
+        float ms;
+    };
+    std::vector<Cand> stage1;
+    for (int G : lanes_c)
+        for (int pl : place_c) {
+            if (rc) break;
+            Choice ch;
+            if (choose_variant(m, G, pl, &ch) != RKC_OK) continue;
+            if (pl == RKC_PARAMS_REGISTERS && ch.v.RUC <= 0) continue;   // fell back to LDS
+            if (pl == RKC_PARAMS_GLOBAL && (G == 1 || !find_variant(ch.v.G, ch.v.NSL, -1)))
+                continue;
+            if (G == 1 && pl != RKC_PARAMS_LDS) continue;   // one placement for one lane per cell
             rkc_opts c = o;
             c.device_ptrs = 1;
             c.cell_counters = nullptr;
-            c.schedule = sched;
-            c.block_groups = std::max(1, gmax / div);
+            c.lanes_per_cell = G;
+            c.param_placement = pl;
+            c.schedule = RKC_SCHED_PERSISTENT;
+            c.block_groups = 0;
             c.grid_blocks = 0;
-            cand.push_back(c);
+            float ms = 0.0f;
+            const int trc = time_it(c, 2, &ms);
+            if (trc == RKC_ENOTSUP) continue;   // does not fit (LDS, variant)
+            if (trc) { rc = trc; break; }
+            stage1.push_back({c, ms});
         }
-    float best = -1.0f;
-    for (size_t i = 0; rc == RKC_OK && i <= cand.size(); ++i) {
-        // i == 0 is an untimed warm-up of the first candidate (first-use tables)
-        const rkc_opts &c = cand[i == 0 ? 0 : i - 1];
-        rkchost::LaunchInfo li;
-        if (hip_failed(hipMemcpyAsync(Tw, T0, 8 * n, hipMemcpyDeviceToDevice, st), "copy", __LINE__) ||
-            hip_failed(hipMemcpyAsync(Yw, Y0, 8 * n * nS, hipMemcpyDeviceToDevice, st), "copy",
-                       __LINE__) ||
-            hip_failed(hipEventRecord(e0, st), "record", __LINE__)) {
-            rc = RKC_EDEVICE;
-            break;
-        }
-        rc = rkchost::enqueue_integrate(m, n, Tw, Pd, Yw, dt, rtol, atol, c, sd, nullptr,
-                                        m->agg_d, m->queue_d, st, &li);
-        if (rc) break;
-        float ms = 0.0f;
-        if (hip_failed(hipEventRecord(e1, st), "record", __LINE__) ||
-            hip_failed(hipEventSynchronize(e1), "sync", __LINE__) ||
-            hip_failed(hipEventElapsedTime(&ms, e0, e1), "elapsed", __LINE__)) {
-            rc = RKC_EDEVICE;
-            break;
-        }
-        if (i > 0 && (best < 0.0f || ms < best)) {
-            best = ms;
-            *tuned = o;
-            tuned->schedule = c.schedule;
-            tuned->block_groups = c.block_groups;
-            tuned->grid_blocks = 0;
+    if (rc == RKC_OK && stage1.empty()) rc = RKC_ENOTSUP;
+    // Stage 2: for the two fastest, both schedules and workgroups of the
+    // largest, half and a quarter of the lane groups (or lanes) they allow.
+    Cand best{o, -1.0f};
+    if (rc == RKC_OK) {
+        std::sort(stage1.begin(), stage1.end(),
+                  [](const Cand &a, const Cand &b) { return a.ms < b.ms; });
+        best = stage1[0];
+        for (size_t k = 0; k < std::min<size_t>(2, stage1.size()) && rc == RKC_OK; ++k) {
+            Choice ch;
+            (void)choose_variant(m, stage1[k].c.lanes_per_cell, stage1[k].c.param_placement, &ch);
+            const int gmax = ch.v.G == 1 ? ch.v.max_threads : std::max(1, ch.v.max_threads / ch.v.G);
+            for (int sched : {RKC_SCHED_PERSISTENT, RKC_SCHED_PLAIN})
+                for (int div : {1, 2, 4}) {
+                    if (sched == RKC_SCHED_PERSISTENT && div == 1) continue;   // stage 1 ran it
+                    const int bg = ch.v.G == 1 ? std::max(64, gmax / div) : std::max(1, gmax / div);
+                    rkc_opts c = stage1[k].c;
+                    c.schedule = sched;
+                    c.block_groups = bg;
+                    float ms = 0.0f;
+                    const int trc = time_it(c, 2, &ms);
+                    if (trc == RKC_ENOTSUP) continue;
+                    if (trc) { rc = trc; break; }
+                    if (ms < best.ms) best = {c, ms};
+                }
         }
     }
     if (e0) (void)hipEventDestroy(e0);
@@ -1457,7 +1521,15 @@ int rkc_autotune(const rkc_mech *mc, size_t n, const double *T, const double *P,
     (void)hipStreamSynchronize(st);
     (void)hipFree(buf);
     if (rc) return rc;
-    if (best_ms) *best_ms = best;
+    *tuned = o;
+    tuned->lanes_per_cell = best.c.lanes_per_cell;
+    tuned->param_placement = best.c.param_placement;
+    tuned->schedule = best.c.schedule;
+    tuned->block_groups = best.c.block_groups;
+    tuned->grid_blocks = 0;
+    m->tuned.push_back({o.method, o.lanes_per_cell, o.param_placement, o.layout, log2n, *tuned,
+                        best.ms});
+    if (best_ms) *best_ms = best.ms;
     return RKC_OK;
 }
 

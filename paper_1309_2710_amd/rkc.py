@@ -388,18 +388,21 @@ def integrate_noalloc(mech, T, P, Y, dt, rtol=1e-6, atol=1e-10, method=RKC, lane
 
 
 def autotune(mech, T, P, Y, dt, rtol=1e-6, atol=1e-10, method=RKC, lanes_per_cell=0,
-             param_placement=PARAMS_AUTO):
+             param_placement=PARAMS_AUTO, layout=LAYOUT_CELL_MAJOR):
     """rkc_autotune on a sample of cells (numpy or torch GPU arrays, left
     unchanged).  Returns (dict of integrate() keyword arguments, best ms)."""
     dev = _is_torch(T)
+    _check_shapes(mech, int(T.shape[0]), P, Y, layout)
     if dev:
         ptrs = [ct.c_void_p(a.data_ptr()) for a in (T, P, Y)]
         o = make_opts(method, lanes_per_cell=lanes_per_cell, device_ptrs=True,
-                      stream=_stream_handle(None, [T]), param_placement=param_placement)
+                      stream=_stream_handle(None, [T]), param_placement=param_placement,
+                      layout=layout)
     else:
         keep = [np.ascontiguousarray(a, np.float64) for a in (T, P, Y)]
         ptrs = [_np_ptr(a) for a in keep]
-        o = make_opts(method, lanes_per_cell=lanes_per_cell, param_placement=param_placement)
+        o = make_opts(method, lanes_per_cell=lanes_per_cell, param_placement=param_placement,
+                      layout=layout)
     t = Opts()
     ms = ct.c_float()
     rc = lib().rkc_autotune(mech.handle, int(T.shape[0]), *ptrs, float(dt), float(rtol),
@@ -407,7 +410,8 @@ def autotune(mech, T, P, Y, dt, rtol=1e-6, atol=1e-10, method=RKC, lanes_per_cel
     if rc != OK:
         raise RkcError(rc, "rkc_autotune")
     return {"schedule": t.schedule, "block_groups": t.block_groups,
-            "grid_blocks": t.grid_blocks}, ms.value
+            "grid_blocks": t.grid_blocks, "lanes_per_cell": t.lanes_per_cell,
+            "param_placement": t.param_placement}, ms.value
 
 
 class Graph:
@@ -458,7 +462,7 @@ class Graph:
 
 
 def divergence(work, width=32, stride=1, stream=None):
-    """Divergence measure D (Sec. 3.2) of runs of `width` consecutive cells.
+    """Divergence measure D (Sec. 3.1) of runs of `width` consecutive cells.
 
     work: per-cell work counts, int32, numpy (host) or torch GPU tensor; a 2-D
     array of counters is read column 0 with its row stride.  Returns D as the

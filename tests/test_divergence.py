@@ -1,4 +1,4 @@
-"""Divergence measure D (Sec. 3.2): the oracle's definition pinned by closed
+"""Divergence measure D (Sec. 3.1): the oracle's definition pinned by closed
 forms, and the library's argument checks on the CPU."""
 import numpy as np
 import pytest

@@ -1,4 +1,4 @@
-"""GPU diagnostics: the divergence measure D (Sec. 3.2) computed by the
+"""GPU diagnostics: the divergence measure D (Sec. 3.1) computed by the
 library against its plain definition, and the issued-evaluation counter of the
 lane-group loop against the per-cell work it must equal."""
 import numpy as np
