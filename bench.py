@@ -372,16 +372,22 @@ def trajectory_states(rkc, gm, c, synth, mech, n_traj, n_samp, seed):
 
 def study_divergence(args):
     """Throughput and divergence D (Sec. 3.1) for ignition-sampled states in
-    trajectory order and shuffled, plain and persistent schedules, on the
-    13-species (16 lanes per cell: 4 cells per wavefront) and the 53-species
-    (64 lanes: one cell per wavefront) sets."""
+    trajectory order and shuffled: the 13-species set with 16-lane groups
+    (plain and persistent schedules) and with one lane per cell (persistent,
+    species-major state), the 53-species set with 64-lane groups (plain and
+    persistent).  D is reported for the paper's 32-thread warps and for the
+    cells a wavefront holds at once (64 / lanes per cell), with histograms of
+    D over ten equal bins of [0, 1] as in the paper's divergence figures."""
     import torch
 
     from paper_1309_2710_amd import rkc, synth
 
     dev = torch.device("cuda:0")
     rows = []
-    for cfg, n_traj in (("c2", 1024), ("c3", 512)):
+    bins = np.linspace(0.0, 1.0, 11)
+    for cfg, n_traj, forms in (("c2", 1024, [(16, rkc.SCHED_PLAIN), (16, rkc.SCHED_PERSISTENT),
+                                             (1, rkc.SCHED_PERSISTENT)]),
+                               ("c3", 512, [(64, rkc.SCHED_PLAIN), (64, rkc.SCHED_PERSISTENT)])):
         c = synth.CONFIGS[cfg]
         mech = synth.config_mechanism(cfg)
         gm = rkc.Mechanism(mech)
@@ -391,76 +397,89 @@ def study_divergence(args):
         for order in ("trajectory", "shuffled"):
             Ti = T0 if order == "trajectory" else T0[perm].contiguous()
             Yi = Y0 if order == "trajectory" else Y0[perm].contiguous()
-            for sched in (rkc.SCHED_PLAIN, rkc.SCHED_PERSISTENT):
-                T, Y = Ti.clone(), Yi.clone()
+            for G, sched in forms:
+                layout = 1 if G == 1 else 0
+                Yl = Yi if layout == 0 else Yi.t().contiguous()
+                T, Y = Ti.clone(), Yl.clone()
                 o = rkc.integrate(gm, T, P, Y, c["dt"], c["rtol"], c["atol"], schedule=sched,
-                                  counters=True, stats=True)
+                                  lanes_per_cell=G, layout=layout, counters=True, stats=True)
                 cn = o["counters"]
-                D32 = rkc.divergence(cn, 32)
-                G = o["stats"]["lanes_per_cell"]
-                Dw = rkc.divergence(cn, 64 // G)
-                T, Y = Ti.clone(), Yi.clone()
+                D32 = rkc.divergence(cn, 32).cpu().numpy()
+                Dw = rkc.divergence(cn, 64 // G).cpu().numpy()
+                T, Y = Ti.clone(), Yl.clone()
                 torch.cuda.synchronize()
                 t = time.perf_counter()
                 for _ in range(args.steps):
                     rkc.integrate(gm, T, P, Y, c["dt"], c["rtol"], c["atol"], schedule=sched,
-                                  status=False)
+                                  lanes_per_cell=G, layout=layout, status=False)
                 torch.cuda.synchronize()
                 wall = time.perf_counter() - t
                 rows.append({"set": "%dsp/%drx" % (mech["n_species"], mech["n_reactions"]),
                              "cells": n, "order": order,
                              "schedule": "plain" if sched == rkc.SCHED_PLAIN else "persistent",
                              "lanes_per_cell": G, "cell_odes_per_s": n * args.steps / wall,
-                             "mean_D32": float(D32.mean().item()),
-                             "mean_D_wave": float(Dw.mean().item()),
+                             "mean_D32": float(D32.mean()), "mean_D_wave": float(Dw.mean()),
+                             "hist_D32": np.histogram(D32, bins)[0].tolist(),
+                             "hist_D_wave": np.histogram(Dw, bins)[0].tolist(),
                              "rhs_utilisation_step1": o["stats"]["n_rhs"] / max(1, o["stats"]["n_rhs_slots"])})
                 print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
     out = {"metric": "divergence study: ignition-sampled states, trajectory order vs shuffled",
            "unit": "cell-ODEs/s", "n_gpus": 1, "steps": args.steps, "dtype": "f64",
-           "data": "synthetic", "rows": rows}
+           "data": "synthetic", "hist_bins": bins.tolist(), "rows": rows}
     print(json.dumps(out), flush=True)
 
 
 def study_crossover(args):
-    """RKC against RKCK as the global step grows (Sec. 3: RKCK suits nonstiff
-    chemistry, RKC moderately stiff): the 9-species and 13-species sets, 65536
-    cells, one global step of dt from the seeded states, both methods at the
-    same tolerance; reports cell-ODEs/s per method and which is faster."""
+    """RKC against RKCK as stiffness and the global step grow (Sec. 3: RKCK
+    suits nonstiff chemistry, RKC moderately stiff; the ethylene case of
+    Sec. 3.4 runs dt = 1e-4 s).  Mechanisms of the 9- and 13-species shapes
+    drawn with stiffness caps lambda_cap of 5, 30 and 100 stages over 1e-6 s;
+    8192 cells of each set's states; one global step of dt = 1e-8 ... 1e-4 s
+    with both methods at the same tolerance and at most 50000 steps per cell.
+    Reports cell-ODEs/s, mean and largest evaluations per cell (a launch lasts
+    as long as its most expensive cell) and which method is faster."""
     import torch
 
     from paper_1309_2710_amd import rkc, synth
 
     dev = torch.device("cuda:0")
     rows = []
+    n = 8192
     for cfg in ("c1", "c2"):
         c = synth.CONFIGS[cfg]
-        mech = synth.config_mechanism(cfg)
-        gm = rkc.Mechanism(mech)
-        st = synth.config_states(cfg)
-        n = min(65536, st["T"].shape[0])
-        T0 = torch.from_numpy(st["T"][:n]).to(dev)
-        P = torch.from_numpy(st["P"][:n]).to(dev)
-        Y0 = torch.from_numpy(st["Y"][:n]).to(dev)
-        for dt in (1e-8, 1e-7, 1e-6, 1e-5):
-            res = {}
-            for name, method in (("rkc", rkc.RKC), ("rkck", rkc.RKCK)):
-                T, Y = T0.clone(), Y0.clone()
-                torch.cuda.synchronize()
-                t = time.perf_counter()
-                o = rkc.integrate(gm, T, P, Y, dt, c["rtol"], c["atol"], method=method,
-                                  stats=True, status=False, counters=True)
-                torch.cuda.synchronize()
-                wall = time.perf_counter() - t
-                # a launch lasts as long as its most expensive cell
-                res[name] = {"cell_odes_per_s": n / wall, "rhs_per_cell": o["stats"]["n_rhs"] / n,
-                             "rhs_max_cell": int(o["counters"][:, 0].max().item()),
-                             "failed": o["stats"]["n_failed"]}
-            row = {"set": "%dsp/%drx" % (mech["n_species"], mech["n_reactions"]), "dt": dt,
-                   "cells": n, "rkc": res["rkc"], "rkck": res["rkck"],
-                   "faster": max(res, key=lambda k: res[k]["cell_odes_per_s"])}
-            rows.append(row)
-            print(json.dumps(row), file=sys.stderr, flush=True)
-    out = {"metric": "RKC vs RKCK crossover in the global step", "unit": "cell-ODEs/s",
+        for s_cap in (5, 30, 100):
+            mech = synth.make_mechanism(c["n_species"], c["n_reactions"], c["elements"],
+                                        c["mech_seed"], ea_max=c["ea_max"], T_lo=c["T_range"][0],
+                                        T_hi=c["T_range"][1], P_max=c["P_max"], dt=1e-6,
+                                        s_target=s_cap, name="%s_cap%d" % (cfg, s_cap))
+            gm = rkc.Mechanism(mech)
+            st = synth.make_states(mech, n, c["state_seed"], T_dist=c["T"], P_dist=c["P"],
+                                   Y_dist=c["Y"])
+            T0 = torch.from_numpy(st["T"]).to(dev)
+            P = torch.from_numpy(st["P"]).to(dev)
+            Y0 = torch.from_numpy(st["Y"]).to(dev)
+            for dt in (1e-8, 1e-7, 1e-6, 1e-5, 1e-4):
+                res = {}
+                for name, method in (("rkc", rkc.RKC), ("rkck", rkc.RKCK)):
+                    T, Y = T0.clone(), Y0.clone()
+                    torch.cuda.synchronize()
+                    t = time.perf_counter()
+                    o = rkc.integrate(gm, T, P, Y, dt, c["rtol"], c["atol"], method=method,
+                                      stats=True, status=False, counters=True, max_steps=50000)
+                    torch.cuda.synchronize()
+                    wall = time.perf_counter() - t
+                    res[name] = {"cell_odes_per_s": n / wall,
+                                 "rhs_per_cell": o["stats"]["n_rhs"] / n,
+                                 "rhs_max_cell": int(o["counters"][:, 0].max().item()),
+                                 "failed": o["stats"]["n_failed"]}
+                ok = [k for k in res if res[k]["failed"] == 0]
+                row = {"set": "%dsp/%drx" % (mech["n_species"], mech["n_reactions"]),
+                       "lambda_cap_stages": s_cap, "lambda_cap": mech["lambda_cap"], "dt": dt,
+                       "cells": n, "rkc": res["rkc"], "rkck": res["rkck"],
+                       "faster": max(ok, key=lambda k: res[k]["cell_odes_per_s"]) if ok else None}
+                rows.append(row)
+                print(json.dumps(row), file=sys.stderr, flush=True)
+    out = {"metric": "RKC vs RKCK crossover in stiffness cap and global step", "unit": "cell-ODEs/s",
            "n_gpus": 1, "dtype": "f64", "data": "synthetic", "rows": rows}
     print(json.dumps(out), flush=True)
 
