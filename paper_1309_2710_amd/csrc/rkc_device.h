@@ -19,6 +19,8 @@
 //   - norms and mixture sums are reductions over the G lanes by DPP exchanges
 //     inside 16-lane rows and DPP row broadcasts across them, so every lane of
 //     a group holds bitwise identical scalars and takes the same decisions.
+//     (ds_swizzle butterflies issue fewer vector instructions but lengthen
+//     the dependent chain; measured slower at four waves per SIMD.)
 // The integrator is written as a state machine in which every iteration of
 // the main loop performs exactly one source-term evaluation for every group
 // of the wave, whatever phase (power iteration, initial step, Chebyshev stage,
@@ -34,6 +36,8 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <type_traits>
 
 namespace rkcdev {
 
@@ -93,6 +97,7 @@ struct Params {
     int nS, N, NK, nU, RU, NSEG, SEGL, L2P, L2N;
     int RUp, NPR, NMS;               // first round with pressure-dependent units, their
                                      // rounds (RUp + NPR = RU), efficiency sets
+    int RU2;                         // rounds [0, RU2): no side has a third reactant slot
     Tables tab;
     int n_cells;
     double *T;
@@ -344,10 +349,18 @@ __device__ __forceinline__ double exp_cw(double x, const ExpK &k) {
 __device__ __forceinline__ double exp_cw(double x) { return exp_cw(x, exp_k()); }
 
 // The same constants as values the compiler cannot see through, so that they
-// are materialised where a source-term evaluation starts (scalar moves) and
-// do not occupy scalar registers across the integrator's bookkeeping.
+// are materialised where a source-term evaluation starts and do not occupy
+// registers across the integrator's bookkeeping.  Most are scalar; the shift
+// and the second polynomial coefficient are vector registers, because each
+// meets another scalar constant in one FMA (x log2e + shift, c0 r + c1) and
+// an instruction reads at most one scalar register.
 __device__ __forceinline__ double opaque_sd(double v) {
     asm volatile("" : "+s"(v));
+    return v;
+}
+
+__device__ __forceinline__ double opaque_vd(double v) {
+    asm volatile("" : "+v"(v));
     return v;
 }
 
@@ -355,11 +368,11 @@ __device__ __forceinline__ ExpK exp_k_local() {
     constexpr ExpK c = exp_k();
     ExpK k;
     k.log2e = opaque_sd(c.log2e);
-    k.shift = opaque_sd(c.shift);
+    k.shift = opaque_vd(c.shift);
     k.ln2hi = opaque_sd(c.ln2hi);
     k.ln2lo = opaque_sd(c.ln2lo);
 #pragma unroll
-    for (int i = 0; i < 10; ++i) k.c[i] = opaque_sd(c.c[i]);
+    for (int i = 0; i < 10; ++i) k.c[i] = (i == 1) ? opaque_vd(c.c[i]) : opaque_sd(c.c[i]);
     return k;
 }
 
@@ -530,7 +543,8 @@ template <int G, int NSL, int RUC, bool PD>
 __device__ __forceinline__ void rhs_eval(const double (&z)[NSL], double P10, double invP10,
                                          double (&fz)[NSL], const GroupLds &L,
                                          const UnitRegs<RUC> &ur, int g, int N, int RU, int NSEG,
-                                         int SEGL, int L2P, int L2N, int RUp, int NMS) {
+                                         int SEGL, int L2P, int L2N, int RUp, int NMS,
+                                         int RU2) {
     constexpr int NK = NSL * G;
     const uint32_t oz = opaque_zero();
     const int go = g + (int)oz;
@@ -621,45 +635,63 @@ __device__ __forceinline__ void rhs_eval(const double (&z)[NSL], double P10, dou
         // ahead; the load after the last unit reads the group arrays that
         // follow the table in LDS and is not used.
         const double2 *ub = reinterpret_cast<const double2 *>(L.units) + g;
-        double2 u3n = ub[3 * G];
-        const int r_fast = PD ? RUp : RU;
-        for (int r = 0; r < r_fast; ++r) {
-            const int p = r * G + g;
+        const unsigned char *Cb = reinterpret_cast<const unsigned char *>(C);
+        auto cat = [&](uint64_t o, int sl) {
+            return *reinterpret_cast<const double *>(Cb + ((o >> (16 * sl)) & 0xffffu));
+        };
+        // one unit from its slots u3 (loaded one unit ahead); returns the next
+        // unit's slots.  Reactant slots first: the concentration products load
+        // and multiply while the two exponentials are computed.  In rounds
+        // [0, RU2) no side has a third reactant, whose slot names the 1.0
+        // entry, so the third factor is left out (multiplying by 1.0 is
+        // exact: the products are the same).
+        auto unit = [&](int r, const double2 u3, auto three) {
             const double2 *u = ub + (size_t)(4 * r) * G;
-            // reactant slots first: the concentration products load and
-            // multiply while the two exponentials are computed
-            const double2 u3 = u3n;
             const double2 u0 = u[0], u1 = u[G], u2 = u[2 * G];
-            u3n = u[7 * G];
+            const double2 u3n = u[7 * G];
             const uint64_t a = __double_as_longlong(u3.x), b = __double_as_longlong(u3.y);
-            const unsigned char *Cb = reinterpret_cast<const unsigned char *>(C);
-            auto cat = [&](uint64_t o, int sl) {
-                return *reinterpret_cast<const double *>(Cb + ((o >> (16 * sl)) & 0xffffu));
-            };
-            const double cf = cat(a, 0) * cat(a, 1) * cat(a, 2);
-            const double cr = cat(b, 0) * cat(b, 1) * cat(b, 2);
+            double cf = cat(a, 0) * cat(a, 1);
+            double cr = cat(b, 0) * cat(b, 1);
+            if constexpr (decltype(three)::value) {
+                cf *= cat(a, 2);
+                cr *= cat(b, 2);
+            }
             const double kf = exp_cw(arrhenius_arg(u0.x, u0.y, u1.x, lnT, invT), K);
             const double kr = exp_cw(arrhenius_arg(u1.y, u2.x, u2.y, lnT, invT), K);
-            Q[p] = net_rate(kf, cf, kr, cr);
+            Q[r * G + g] = net_rate(kf, cf, kr, cr);
+            return u3n;
+        };
+        const std::integral_constant<bool, false> two_slots;
+        const std::integral_constant<bool, true> three_slots;
+        const int r_fast = PD ? RUp : RU;
+        // two units per iteration, so that the prefetched slots alternate
+        // between two registers instead of being copied every unit
+        double2 u3a = ub[3 * G];
+        int r = 0;
+        for (; r + 1 < RU2; r += 2) {
+            const double2 u3b = unit(r, u3a, two_slots);
+            u3a = unit(r + 1, u3b, two_slots);
         }
+        if (r < RU2) u3a = unit(r++, u3a, two_slots);
+        for (; r + 1 < r_fast; r += 2) {
+            const double2 u3b = unit(r, u3a, three_slots);
+            u3a = unit(r + 1, u3b, three_slots);
+        }
+        if (r < r_fast) (void)unit(r, u3a, three_slots);
         // rounds with pressure-dependent units: third body and falloff (only
         // in the kernels built for mechanisms that have them)
         if constexpr (PD)
-        for (int r = RUp; r < RU; ++r) {
-            const int p = r * G + g;
-            const double2 *u = ub + (size_t)(4 * r) * G;
+        for (int rp = RUp; rp < RU; ++rp) {
+            const int p = rp * G + g;
+            const double2 *u = ub + (size_t)(4 * rp) * G;
             const double2 u0 = u[0], u1 = u[G], u2 = u[2 * G], u3 = u[3 * G];
             const uint64_t a = __double_as_longlong(u3.x), b = __double_as_longlong(u3.y);
-            const unsigned char *Cb = reinterpret_cast<const unsigned char *>(C);
-            auto cat = [&](uint64_t o, int sl) {
-                return *reinterpret_cast<const double *>(Cb + ((o >> (16 * sl)) & 0xffffu));
-            };
             const double cf = cat(a, 0) * cat(a, 1) * cat(a, 2);
             const double cr = cat(b, 0) * cat(b, 1) * cat(b, 2);
             double kf = exp_cw(arrhenius_arg(u0.x, u0.y, u1.x, lnT, invT), K);
             double kr = exp_cw(arrhenius_arg(u1.y, u2.x, u2.y, lnT, invT), K);
             const double2 *pd = reinterpret_cast<const double2 *>(L.pdep) +
-                                (size_t)(6 * (r - RUp)) * G + g;
+                                (size_t)(6 * (rp - RUp)) * G + g;
             const double2 d0 = pd[0];
             const uint64_t tag = __double_as_longlong(d0.x);
             const int kind = (int)(tag & 0xffu);
@@ -924,7 +956,7 @@ __global__ __launch_bounds__((Occ<RUC, NSL>::threads), (Occ<RUC, NSL>::waves)) v
     if (!active) z[0] = (g == 0) ? 1000.0 : z[0];
     const double P10 = active ? p.P[cell] * 10.0 : 1e6;
     rhs_eval<G, NSL, RUC, PD>(z, P10, 1.0 / P10, fz, L, ur, g, p.N, p.RU, p.NSEG, p.SEGL, p.L2P,
-                              p.L2N, p.RUp, p.NMS);
+                              p.L2N, p.RUp, p.NMS, p.RU2);
     if (active) {
 #pragma unroll
         for (int s = 0; s < NSL; ++s) {

@@ -27,6 +27,7 @@ constexpr double TROE_BOUND = 1e10;        // largest 1/T***, 1/T* and T** passe
 struct NkTables {
     int G = 0, NK = 0, RU = 0, NSEG = 0, SEGL = 0, L2P = 0, L2N = 0;
     int RUp = 0, NPR = 0, NMS = 0;   // pressure-dependent rounds and efficiency sets
+    int RU2 = 0;                     // rounds [0, RU2) of units with two slots a side
     double *spec = nullptr;
     uint32_t *gather = nullptr;
     uint32_t *gather2 = nullptr;
@@ -50,6 +51,7 @@ struct rkc_mech {
     int nS = 0, nR = 0, N = 0, nU = 0, nU_pad = 0, nnz = 0, max_row = 0;
     std::vector<double> units_h;                       // [nU_pad][8]
     int n_plain = 0, n_pdep = 0;                       // units [0, n_plain) plain, then pdep
+    int n_two = 0;   // units [0, n_two) plain with at most two reactant slots per side
     std::vector<double> pdep_h;                        // [n_pdep][PDEP_DOUBLES]
     std::vector<std::vector<double>> effsets;          // distinct efficiency vectors [nS]
     double *pdep_d = nullptr;
@@ -354,6 +356,7 @@ int ensure_tables(rkc_mech *m, int G, int NK, int RU, NkTables **out, bool may_b
     t.NMS = (int)m->effsets.size();
     t.RUp = m->n_pdep > 0 ? m->n_plain / G : RU;
     t.NPR = RU - t.RUp;
+    t.RU2 = std::min(m->n_two / G, t.RUp);
     std::vector<double> pd((size_t)t.NPR * G * rkcdev::PDEP_DOUBLES, 0.0);
     for (int l = 0; l < t.NPR * G; ++l) {
         const int unit = t.RUp * G + l;
@@ -734,6 +737,7 @@ void fill_params(const rkc_mech *m, const Choice &ch, const NkTables *nk, rkcdev
     p->tab.pdep = nk->pdep;
     p->tab.eff = nk->eff;
     p->RUp = nk->RUp;
+    p->RU2 = nk->RU2;
     p->NPR = nk->NPR;
     p->NMS = nk->NMS;
     p->agg = m->agg_d;
@@ -990,6 +994,7 @@ int rkc_mech_create(const rkc_mech_desc *d, rkc_mech **out) {
         double rec[UNIT_DOUBLES];
         double pd[rkcdev::PDEP_DOUBLES];
         int kind;
+        int three;                              // a side with three reactant slots
         std::vector<std::pair<int, int>> dnu;   // (species, nu'' - nu')
     };
     auto kind_of = [&](int j) { return d->pdep ? d->pdep[j] : RKC_PDEP_PLAIN; };
@@ -1026,6 +1031,8 @@ int rkc_mech_create(const rkc_mech_desc *d, rkc_mech **out) {
             u.rec[3] = LNA_ZERO;
             idr = pack_slots(none, nS);
         }
+        auto n_slots = [](const int32_t *x) { return (x[0] >= 0) + (x[1] >= 0) + (x[2] >= 0); };
+        u.three = n_slots(rf) == 3 || (pair && n_slots(d->reac + 3 * (j + 1)) == 3);
         const uint64_t idf = pack_slots(rf, nS);
         std::memcpy(&u.rec[6], &idf, 8);
         std::memcpy(&u.rec[7], &idr, 8);
@@ -1066,8 +1073,11 @@ int rkc_mech_create(const rkc_mech_desc *d, rkc_mech **out) {
         srcs.push_back(u);
         j += pair ? 2 : 1;
     }
-    std::stable_sort(srcs.begin(), srcs.end(),
-                     [](const UnitSrc &x, const UnitSrc &y) { return x.kind < y.kind; });
+    // plain units with at most two reactant slots on each side first: whole
+    // rounds of them skip the third concentration factor (always the 1.0 slot)
+    std::stable_sort(srcs.begin(), srcs.end(), [](const UnitSrc &x, const UnitSrc &y) {
+        return x.kind != y.kind ? x.kind < y.kind : x.three < y.three;
+    });
     if (m->effsets.size() > (size_t)rkcdev::MAX_EFFSETS) { delete m; return RKC_ENOTSUP; }
     std::vector<double> units;
     int p = 0;
@@ -1075,6 +1085,7 @@ int rkc_mech_create(const rkc_mech_desc *d, rkc_mech **out) {
         units.insert(units.end(), u.rec, u.rec + UNIT_DOUBLES);
         if (u.kind != RKC_PDEP_PLAIN) m->pdep_h.insert(m->pdep_h.end(), u.pd, u.pd + rkcdev::PDEP_DOUBLES);
         else ++m->n_plain;
+        if (u.kind == RKC_PDEP_PLAIN && !u.three) ++m->n_two;
         for (const auto &e : u.dnu) m->rows[e.first].push_back({p, e.second});
         ++p;
     }

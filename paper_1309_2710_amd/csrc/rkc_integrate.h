@@ -262,7 +262,7 @@ __global__ __launch_bounds__((Occ<RUC, NSL>::threads), (Occ<RUC, NSL>::waves)) v
         {
             ParamsK &pr = *params_k();
             rhs_eval<G, NSL, RUC, PD>(z, S.P10, S.invP10, fz, L, ur, g, N, pr.RU, pr.NSEG, pr.SEGL,
-                                      pr.L2P, pr.L2N, pr.RUp, pr.NMS);
+                                      pr.L2P, pr.L2N, pr.RUp, pr.NMS, pr.RU2);
         }
         if (S.cell >= 0) {
             ParamsK &pk = *params_k();
@@ -631,7 +631,7 @@ __global__ __launch_bounds__((Occ<RUC, NSL>::threads), (Occ<RUC, NSL>::waves)) v
         if (!__any(S.cell >= 0)) break;   // a wave whose groups hold no cell issues nothing
         ++iters;
         rhs_eval<G, NSL, RUC, PD>(z, S.P10, S.invP10, fz, L, ur, g, N, p.RU, p.NSEG, p.SEGL,
-                                  p.L2P, p.L2N, p.RUp, p.NMS);
+                                  p.L2P, p.L2N, p.RUp, p.NMS, p.RU2);
         if (S.cell >= 0) {
             Counts c = S.c;
             c.n_rhs += 1;

@@ -50,6 +50,18 @@ GPU_COL = {"n_rhs": 0, "n_steps": 1, "n_reject": 2, "n_sigma": 3, "s_max_used": 
            "status": 6, "n_power_iter": 7}
 
 
+def mass_drift_bound(n_rhs):
+    """Largest change of sum_i Y_i a cell may show after n_rhs source-term
+    evaluations.  The species equations conserve mass exactly (the net
+    production weighted by the molecular weights sums to zero for
+    mass-balanced reactions), so the drift is rounding: every stage update
+    (E:rkcj) rounds each component a few times at magnitudes up to about
+    2 |y| and uses 1 - mu - nu rounded, a few units of 2^-53 per update in a
+    sum of mass fractions equal to 1, accumulated over the evaluations of the
+    cell.  16 units per evaluation, and never below 1e-12."""
+    return np.maximum(1e-12, 16.0 * 2.0 ** -53 * np.asarray(n_rhs, dtype=np.float64))
+
+
 def rel_err(Tg, Yg, To, Yo, floor=Y_FLOOR):
     eT = np.abs(Tg - To) / np.abs(To)
     eY = np.abs(Yg - Yo) / np.maximum(np.abs(Yo), floor)

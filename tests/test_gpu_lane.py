@@ -235,7 +235,8 @@ def test_full_size_c2_sampled_lane(R):
     assert out["stats"]["n_failed"] == 0
     Th = T.cpu().numpy()
     Yh = np.ascontiguousarray(Y.cpu().numpy().T)
-    assert np.abs(Yh.sum(1) - st["Y"].sum(1)).max() <= 1e-12
+    drift = np.abs(Yh.sum(1) - st["Y"].sum(1))
+    assert (drift <= PT.mass_drift_bound(out["counters"].cpu().numpy()[:, 0])).all()
     idx = np.random.default_rng(17).choice(n, 256, replace=False)
     To, Yo, co = O.Model(m).integrate(st["T"][idx], st["P"][idx], st["Y"][idx], c["dt"],
                                       c["rtol"], c["atol"], threads=THREADS)

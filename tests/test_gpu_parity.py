@@ -177,7 +177,10 @@ def _full_size_sampled(R, cfg, n_sample, method=O.RKC):
     cg = out["counters"].cpu().numpy()
     _say("stats", out["stats"])
     assert (out["status"].cpu().numpy() == 0).all()
-    assert np.abs(Yg.sum(1) - st["Y"].sum(1)).max() <= 1e-12
+    drift = np.abs(Yg.sum(1) - st["Y"].sum(1))
+    _say("mass drift max %.3g, largest fraction of its bound %.3f"
+         % (drift.max(), (drift / PT.mass_drift_bound(cg[:, 0])).max()))
+    assert (drift <= PT.mass_drift_bound(cg[:, 0])).all()
     idx = np.arange(0, n, n // n_sample)[:n_sample]
     To, Yo, co = om.integrate(st["T"][idx], st["P"][idx], st["Y"][idx], c["dt"], c["rtol"],
                               c["atol"], method=method, threads=THREADS)
