@@ -99,8 +99,11 @@ def measured_traffic(workload):
 
 
 def stage_flops(mech):
-    """Flops of one RKC stage update (E:rkcj) per RHS evaluation: 1 mul + 4 FMA
-    per state component."""
+    """Flops of the state update per RHS evaluation, 9 per state component.
+    RKC (E:rkcj): 1 mul + 4 FMA per stage.  RKCK (Table 1): per step and
+    component, 15 FMAs for the inputs of stages 2-6, 4 for the fifth-order
+    solution and 5 for the embedded error, about 53 flops with the error
+    scale, over 6 evaluations: also about 9."""
     return 9 * (mech["n_species"] + 1)
 
 
@@ -114,6 +117,14 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c3")
+    ap.add_argument("--cells", type=int, default=None,
+                    help="cells of the workload (default: the configuration's)")
+    ap.add_argument("--method", choices=["rkc", "rkck"], default="rkc",
+                    help="integrator: RKC (Sec. 2.4, default) or RKCK (Sec. 2.3)")
+    ap.add_argument("--dt", type=float, default=None,
+                    help="global step in s (default: the configuration's)")
+    ap.add_argument("--rtol", type=float, default=None,
+                    help="relative tolerance, epsilon for RKCK (default: the configuration's)")
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--schedule", type=int, default=0)
     ap.add_argument("--params", type=int, default=0, help="0 auto, 1 registers, 2 LDS, 3 global memory")
@@ -171,9 +182,16 @@ def main():
         return
 
     cfg = args.config
-    c = synth.CONFIGS[cfg]
+    c = dict(synth.CONFIGS[cfg])
+    if args.dt is not None:
+        c["dt"] = args.dt
+    if args.rtol is not None:
+        c["rtol"] = args.rtol
+    method = rkc.RKCK if args.method == "rkck" else rkc.RKC
+    default_run = (args.method == "rkc" and args.dt is None and args.rtol is None and
+                   args.cells is None)
     mech = synth.config_mechanism(cfg)
-    st = synth.config_states(cfg)
+    st = synth.config_states(cfg, args.cells)
     n = st["T"].shape[0]
     dev = torch.device("cuda:0")
     gm = rkc.Mechanism(mech)
@@ -184,7 +202,7 @@ def main():
     T = T0.clone()
     Y = Y0.clone()
     kw = dict(lanes_per_cell=args.lanes, schedule=args.schedule, status=False,
-              param_placement=args.params, layout=layout)
+              param_placement=args.params, layout=layout, method=method)
     tuned = None
     if args.autotune:
         idx = torch.arange(0, n, max(1, n // 16384), device=dev)[:16384]
@@ -192,7 +210,8 @@ def main():
         t_tune = time.perf_counter()
         tuned, tuned_ms = rkc.autotune(gm, T0[idx].contiguous(), P[idx].contiguous(),
                                        Ys.contiguous(), c["dt"], c["rtol"], c["atol"],
-                                       lanes_per_cell=args.lanes, param_placement=args.params)
+                                       method=method, lanes_per_cell=args.lanes,
+                                       param_placement=args.params)
         tuned["tuning_s"] = time.perf_counter() - t_tune
         tuned["sample_cells"] = int(idx.shape[0])
         if tuned["lanes_per_cell"] != kw["lanes_per_cell"] and layout == 1 and \
@@ -223,7 +242,7 @@ def main():
 
     graph = None
     if args.graph:
-        graph = rkc.Graph(gm, T, P, Y, c["dt"], c["rtol"], c["atol"],
+        graph = rkc.Graph(gm, T, P, Y, c["dt"], c["rtol"], c["atol"], method=method,
                           lanes_per_cell=kw["lanes_per_cell"], schedule=kw["schedule"],
                           block_groups=kw.get("block_groups", 0),
                           param_placement=kw["param_placement"], layout=layout)
@@ -294,7 +313,12 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "RKC, %s" % c["label"], "n_cells": n,
+        "config": {"workload": "%s, %s" % (args.method.upper(), c["label"] if
+                                           default_run or (args.dt is None and args.cells is None)
+                                           else "%dsp/%drx, %d cells, dt %g" % (
+                                               mech["n_species"], mech["n_reactions"], n,
+                                               c["dt"])),
+                   "n_cells": n,
                    "n_species": mech["n_species"], "n_reactions": mech["n_reactions"],
                    "dt": c["dt"], "rtol": c["rtol"], "atol": c["atol"],
                    "lanes_per_cell": census[0]["lanes_per_cell"],
@@ -305,7 +329,9 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
-                     "traffic": measured_traffic(workload_tag(mech, n))},
+                     # the committed traffic summaries cover the default RKC runs
+                     "traffic": measured_traffic(workload_tag(mech, n)) if default_run
+                     else None},
         "pcie_inclusive": pcie,
         "fp64_probe": fp64_probe(),
         "work": {"rhs_evals_per_step": tot_rhs / args.steps, "flops_per_rhs": f_rhs,
@@ -316,11 +342,12 @@ def main():
                  "rhs_utilisation": tot_rhs / max(1, sum(s["n_rhs_slots"] for s in census)),
                  "s_max_used": max(s["s_max_used"] for s in census)},
     }
-    if args.served_requests > 0 and args.config == "c3" and not args.graph:
+    if args.served_requests > 0 and args.config == "c3" and not args.graph and default_run:
         del T, Y, T0, Y0, P
         out["served"] = served_block(args.served_requests, args.served_util)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(mech, c, st, args.steps, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(mech, c, st, args.steps, args.cpu_seconds,
+                                           method=args.method)
     print(json.dumps(out), flush=True)
 
 
@@ -723,12 +750,13 @@ def serve(args):
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(mech, c, st, steps, budget_s):
+def cpu_baseline(mech, c, st, steps, budget_s, method="rkc"):
     """The serial FP64 oracle (unchanged; cells split over host threads) on a
     strided sample of the same workload, K consecutive global steps."""
     from oracle import oracle as O
 
     M = O.Model(mech)
+    om = O.RKCK if method == "rkck" else O.RKC
     # the host cores this process may use (affinity), within the 16-core
     # share the GPU host gives one GPU's job
     try:
@@ -751,7 +779,8 @@ def cpu_baseline(mech, c, st, steps, budget_s):
         P = st["P"][idx]
         t = time.perf_counter()
         for _ in range(steps):
-            T, Y, _ = M.integrate(T, P, Y, c["dt"], c["rtol"], c["atol"], threads=threads)
+            T, Y, _ = M.integrate(T, P, Y, c["dt"], c["rtol"], c["atol"], method=om,
+                                  threads=threads)
         return time.perf_counter() - t
 
     # one host core on a small strided sample (the per-cell code is serial)
@@ -759,7 +788,8 @@ def cpu_baseline(mech, c, st, steps, budget_s):
     T1, Y1 = st["T"][one].copy(), st["Y"][one].copy()
     t1 = time.perf_counter()
     for _ in range(steps):
-        T1, Y1, _ = M.integrate(T1, st["P"][one], Y1, c["dt"], c["rtol"], c["atol"], threads=1)
+        T1, Y1, _ = M.integrate(T1, st["P"][one], Y1, c["dt"], c["rtol"], c["atol"], method=om,
+                                threads=1)
     one_core = len(one) * steps / (time.perf_counter() - t1)
 
     probe = np.arange(0, n, max(1, n // (4 * threads)))[:4 * threads]
