@@ -338,6 +338,9 @@ def main():
                  "flops_per_stage_update": f_stage,
                  "mean_rhs_per_cell": tot_rhs / args.steps / n,
                  "kernel_ms_per_step": step_ms,
+                 # per-launch batch latency of the timed global steps
+                 "step_ms_p50": float(np.percentile(step_ms, 50)),
+                 "step_ms_p99": float(np.percentile(step_ms, 99)),
                  "steps_per_cell": sum(s["n_steps"] for s in census) / args.steps / n,
                  "rhs_utilisation": tot_rhs / max(1, sum(s["n_rhs_slots"] for s in census)),
                  "s_max_used": max(s["s_max_used"] for s in census)},
