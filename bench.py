@@ -343,7 +343,10 @@ def main():
                  "step_ms_p99": float(np.percentile(step_ms, 99)),
                  "steps_per_cell": sum(s["n_steps"] for s in census) / args.steps / n,
                  "rhs_utilisation": tot_rhs / max(1, sum(s["n_rhs_slots"] for s in census)),
-                 "s_max_used": max(s["s_max_used"] for s in census)},
+                 "s_max_used": max(s["s_max_used"] for s in census),
+                 # cells that ended with a failure status (MAXSTEPS, UNDERFLOW,
+                 # NONFINITE) over the timed steps; 0 for every default run
+                 "failed_cells": int(sum(s["n_failed"] for s in census))},
     }
     if args.served_requests > 0 and args.config == "c3" and not args.graph and default_run:
         del T, Y, T0, Y0, P
