@@ -57,6 +57,35 @@ def rhs_flops(mech):
                 d[s] = d.get(s, 0) + 1
         nnz += sum(1 for v in d.values() if v != 0)
     f += 2 * nnz + 28 * nS + 10
+    return f + pdep_flops(mech)
+
+
+LOG_FLOPS = EXP_FLOPS           # a natural logarithm counted like an exponential
+
+
+def pdep_flops(mech):
+    """Algorithmic flops of the pressure-dependent rates per evaluation
+    (Chemkin forms, Sec. 2.2), per forward/reverse pair by kind, 0 for plain
+    mechanisms.  Third-body concentration of each distinct efficiency set: 2
+    per species.  Third body: [M] times both rate constants, 2.  Lindemann:
+    both low-pressure constants (argument 4 + exp each), and per direction
+    k0 [M], Pr = k0 [M] / kinf, 1 + Pr, Pr / (1 + Pr) and the product with kinf,
+    5.  Troe adds the centre value (three exponentials with their arguments
+    and the sum, 3 exp + 7), its log10 (log + 1), c and n (4), and per
+    direction log10 Pr (log + 1), x, f = x / (n - 0.14 x), 1 + f^2, the
+    quotient, the scaling to a natural exponent (8) and exp (exp + 1 for the
+    product with the Lindemann rate)."""
+    if mech.get("pdep") is None:
+        return 0
+    kind = np.asarray(mech["pdep"])[0::2]
+    f = 0
+    lind = 2 * (4 + EXP_FLOPS) + 2 * 5
+    troe = lind + (3 * EXP_FLOPS + 7) + (LOG_FLOPS + 1) + 4 + 2 * (LOG_FLOPS + 1 + 8 + EXP_FLOPS + 1)
+    f += 2 * int((kind == 1).sum()) + lind * int((kind == 2).sum()) + troe * int((kind == 3).sum())
+    if mech.get("eff") is not None:
+        eff = np.asarray(mech["eff"])[0::2][kind > 0]
+        n_sets = len({tuple(r) for r in eff})
+        f += 2 * mech["n_species"] * n_sets
     return f
 
 
