@@ -212,10 +212,16 @@ int rkc_opts_default(rkc_opts *opts);
 /* Validate a mechanism, pack its tables and upload them to the current HIP
  * device.  On success *out owns device memory until rkc_mech_destroy.
  * Errors: RKC_EINVAL (sizes < 1, index out of range, > 3 molecules per side,
- * W <= 0, non-finite parameter, A < 0, a pdep kind outside 0..3, a falloff
- * reaction without A0/beta0/Ea0, a Troe reaction without troe or with
- * T3 <= 0 or T1 <= 0, a negative efficiency), RKC_ENOTSUP (n_species > 1021),
- * RKC_ENOMEM, RKC_EDEVICE. */
+ * W <= 0, non-finite parameter, A < 0, |beta| or |beta0| > 1e5, a pdep kind
+ * outside 0..3, a falloff reaction without A0/beta0/Ea0, a Troe reaction
+ * without troe or with T3 <= 0 or T1 <= 0, a negative efficiency),
+ * RKC_ENOTSUP (n_species > 1021), RKC_ENOMEM, RKC_EDEVICE.
+ * The kernels evaluate every Arrhenius factor with 1/T bounded by
+ * (2^30 - max|log2 A| - 1075 max|beta|) / max|Ea/R log2(e)| over the
+ * mechanism's reactions and low-pressure limits (for activation energies up
+ * to 1e6 J/mol a bound above 5e3 1/K, i.e. temperatures below 2e-4 K are
+ * treated as that temperature in these factors only); this keeps every
+ * base-2 exponent below 2^30 in magnitude. */
 int rkc_mech_create(const rkc_mech_desc *desc, rkc_mech **out);
 
 /* Release a mechanism; NULL is accepted. */

@@ -56,8 +56,8 @@ enum {
 };
 
 // Reaction unit record: 8 doubles.
-//   [0..2] ln A, beta, theta = Ea/R of the forward reaction
-//   [3..5] the same for the reverse reaction (ln A = -1e4 for an unpaired
+//   [0..2] log2 A, beta, theta' = (Ea/R) log2(e) of the forward reaction
+//   [3..5] the same for the reverse reaction (log2 A = -1e4 for an unpaired
 //          reaction, so its reverse rate underflows to exactly zero)
 //   [6]    bit pattern: forward reactant slots, three 16-bit byte offsets
 //          into the concentration array (bits 0..47); an empty slot points
@@ -68,9 +68,10 @@ constexpr int UNIT_DOUBLES = 8;
 // Pressure-dependent unit record (third body and falloff), 12 doubles:
 //   [0] bit pattern: kind (bits 0..7; 1 third body, 2 Lindemann, 3 Troe) and
 //       efficiency set (bits 8..15)
-//   [1..3] ln A0, beta0, theta0 of the forward low-pressure limit k_0
-//   [4..6] the same for the reverse reaction (ln A0 = -1e4 if unpaired)
-//   [7] unused; [8..11] Troe a, 1/T3, 1/T1, T2 (T2 <= 0: term absent)
+//   [1..3] log2 A0, beta0, theta0' of the forward low-pressure limit k_0
+//   [4..6] the same for the reverse reaction (log2 A0 = -1e4 if unpaired)
+//   [7] unused; [8..11] Troe a, log2(e)/T***, log2(e)/T*, T** log2(e)
+//       (T** <= 0: term absent)
 // Units of the rounds that hold pressure-dependent units have one record each
 // (kind 0 for the plain ones there), lane-interleaved like the unit records.
 constexpr int PDEP_DOUBLES = 12;
@@ -98,6 +99,8 @@ struct Params {
     int RUp, NPR, NMS;               // first round with pressure-dependent units, their
                                      // rounds (RUp + NPR = RU), efficiency sets
     int RU2;                         // rounds [0, RU2): no side has a third reactant slot
+    double invTmax;                  // bound on the 1/T of the Arrhenius factors (keeps
+                                     // every base-2 exponent below 2^30 in magnitude)
     Tables tab;
     int n_cells;
     double *T;
@@ -262,7 +265,7 @@ __device__ __forceinline__ double gbcast0(double x) {
 // Registers holding the reaction parameters of a lane's units (RUC > 0).
 template <int RUC>
 struct UnitRegs {
-    double lnAf[RUC], bf[RUC], tf[RUC], lnAr[RUC], br[RUC], tr[RUC];
+    double l2Af[RUC], bf[RUC], tf[RUC], l2Ar[RUC], br[RUC], tr[RUC];
     uint32_t idf[RUC], idr[RUC];
 };
 template <>
@@ -283,13 +286,14 @@ struct GroupLds {
     double *piece;         // [NSEG * G + 2]: partial sums of the gather, then a zero slot
 };
 
-// ln k = ln A + beta ln T - theta/T (E:rxn-const) and the net rate of a
-// forward/reverse pair, each with its roundings written out as FMAs: left to
-// the compiler, the contraction of a sum of products may differ between
+// log2 k = log2 A + beta log2 T - theta' / T (E:rxn-const in base 2, with
+// theta' = theta log2(e) and log2 A stored per reaction) and the net rate of
+// a forward/reverse pair, each with its roundings written out as FMAs: left
+// to the compiler, the contraction of a sum of products may differ between
 // kernel variants, and every variant must form the same values.
-__device__ __forceinline__ double arrhenius_arg(double lnA, double beta, double theta, double lnT,
-                                                double invT) {
-    return __builtin_fma(-theta, invT, __builtin_fma(beta, lnT, lnA));
+__device__ __forceinline__ double arrhenius_arg(double l2A, double beta, double theta2,
+                                                double l2T, double invT) {
+    return __builtin_fma(-theta2, invT, __builtin_fma(beta, l2T, l2A));
 }
 
 __device__ __forceinline__ double net_rate(double kf, double cf, double kr, double cr) {
@@ -300,30 +304,36 @@ __device__ __forceinline__ double unpack_c(const double *C, uint32_t id, int s) 
     return C[(id >> (10 * s)) & 1023u];
 }
 
-// exp(x): Cody & Waite reduction x = n ln2 + r, |r| <= ln2/2, with ln2 split
-// into its double rounding and the remainder, then exp(r) = 1 + r + r^2 q(r)
-// with q a degree-9 Chebyshev fit of (exp(r) - 1 - r)/r^2 on the reduced
-// interval (relative error below 1.6e-17; fit_exp_poly.py prints the
-// coefficients), by Horner, scaled by 2^n.  Within about one ulp; written so
-// every Horner step is one FMA.  n is rounded by adding 1.5 * 2^52 inside the
-// FMA that forms x/ln2.  The exponent of the final scaling is n converted to
-// int32 with saturation (v_cvt_i32_f64 clamps out-of-range values), so for
-// every |x| < 1e16 the result is exact to the above bound: 0 below about
-// -745, +inf above about 709.8 (there |r| stays below 0.3, as the rounding
-// error of n ln2 is far below ln2 / 2); NaN propagates (the conversion gives
-// 0, the polynomial NaN).  Callers keep |x| below 1e16: the Arrhenius
-// argument does for any temperature above 1e-10 K, the Troe terms through the
-// bounds the host puts on 1/T*** , 1/T* and T**.
+// 2^y: y = n + f with n = round(y), rounded by adding 1.5 * 2^52, and
+// f = y - n, which is exact (|f| <= 1/2); then 2^f = 1 + f (L + f q(f)) with
+// L = ln 2 and q a degree-9 Chebyshev fit of (2^f - 1 - f ln 2)/f^2 on
+// [-1/2, 1/2] (relative error below 2.7e-17; fit_exp_poly.py prints the
+// coefficients), by Horner, scaled by 2^n.  Within about one ulp; every
+// Horner step is one FMA.  The rate constants are exponentials of sums that
+// already carry a rounding of order |y| 2^-53, so a base-2 argument formed
+// from base-2 parameters loses nothing against a two-part ln 2 reduction of
+// a natural-log argument, and saves its extra FMA.
+//
+// Two ways of applying 2^n:
+// * exp2_sat: n converted to int32 with saturation (v_cvt_i32_f64 clamps),
+//   so every |y| < 2^51 gives 0 below about -1075, +inf above 1024 (and
+//   larger |y| keep f within a few units, the polynomial positive for
+//   positive f, so the result still saturates); NaN propagates.
+// * exp2_b31: the exponent is the low word of y + 1.5 * 2^52, which holds n
+//   in two's complement while |n| < 2^31, without a conversion.  Callers
+//   keep |y| below 2^30: the Arrhenius factors do through the bound on 1/T
+//   that the host derives from the mechanism's largest log2 A, |beta| and
+//   theta' (|log2 T| <= 1075 for any positive double).
 struct ExpK {
-    double log2e, shift, ln2hi, ln2lo, c[10];
+    double shift, ln2, c[10];
 };
 
 __host__ __device__ constexpr ExpK exp_k() {
-    return ExpK{0x1.71547652b82fep+0, 0x1.8p52, 0x1.62e42fefa39efp-1, 0x1.abc9e3b39803fp-56,
-                {2.5100375832561234e-08, 2.7620075879983367e-07, 2.7557268480310024e-06,
-                 2.4801521322368692e-05, 0.00019841269863040545, 0.0013888888917196719,
-                 0.008333333333330065, 0.041666666666624164, 0.16666666666666669,
-                 0.5000000000000001}};
+    return ExpK{0x1.8p52, 0.6931471805599453,
+                {4.45410341058704e-10, 7.070977866508138e-09, 1.0178067267449427e-07,
+                 1.3215451633221434e-06, 1.5252733820795803e-05, 0.00015403530424776529,
+                 0.0013333558146423213, 0.009618129107618665, 0.05550410866482158,
+                 0.24022650695910075}};
 }
 
 // n (an integral double) to int32, saturating at the int32 range (the
@@ -334,26 +344,33 @@ __device__ __forceinline__ int cvt_sat_i32(double n) {
     return i;
 }
 
-__device__ __forceinline__ double exp_cw(double x, const ExpK &k) {
-    const double t = __builtin_fma(x, k.log2e, k.shift);
-    const double n = t - k.shift;
-    const double r = __builtin_fma(-n, k.ln2lo, __builtin_fma(-n, k.ln2hi, x));
+__device__ __forceinline__ double exp2_frac(double f, const ExpK &k) {
     double q = k.c[0];
 #pragma unroll
-    for (int i = 1; i < 10; ++i) q = __builtin_fma(q, r, k.c[i]);
-    q = __builtin_fma(q, r, 1.0);
-    q = __builtin_fma(q, r, 1.0);
-    return __builtin_ldexp(q, cvt_sat_i32(n));
+    for (int i = 1; i < 10; ++i) q = __builtin_fma(q, f, k.c[i]);
+    q = __builtin_fma(q, f, k.ln2);
+    return __builtin_fma(q, f, 1.0);
 }
 
-__device__ __forceinline__ double exp_cw(double x) { return exp_cw(x, exp_k()); }
+__device__ __forceinline__ double exp2_sat(double y, const ExpK &k) {
+    const double t = y + k.shift;
+    const double n = t - k.shift;
+    return __builtin_ldexp(exp2_frac(y - n, k), cvt_sat_i32(n));
+}
+
+__device__ __forceinline__ double exp2_b31(double y, const ExpK &k) {
+    const double t = y + k.shift;
+    const double n = t - k.shift;
+    return __builtin_ldexp(exp2_frac(y - n, k), (int)(uint32_t)__double_as_longlong(t));
+}
+
+__device__ __forceinline__ double exp2_sat(double y) { return exp2_sat(y, exp_k()); }
 
 // The same constants as values the compiler cannot see through, so that they
 // are materialised where a source-term evaluation starts and do not occupy
-// registers across the integrator's bookkeeping.  Most are scalar; the shift
-// and the second polynomial coefficient are vector registers, because each
-// meets another scalar constant in one FMA (x log2e + shift, c0 r + c1) and
-// an instruction reads at most one scalar register.
+// registers across the integrator's bookkeeping.  All are scalar but the
+// second polynomial coefficient, which meets the first in one FMA
+// (c0 f + c1): an instruction reads at most one scalar register.
 __device__ __forceinline__ double opaque_sd(double v) {
     asm volatile("" : "+s"(v));
     return v;
@@ -367,36 +384,33 @@ __device__ __forceinline__ double opaque_vd(double v) {
 __device__ __forceinline__ ExpK exp_k_local() {
     constexpr ExpK c = exp_k();
     ExpK k;
-    k.log2e = opaque_sd(c.log2e);
-    k.shift = opaque_vd(c.shift);
-    k.ln2hi = opaque_sd(c.ln2hi);
-    k.ln2lo = opaque_sd(c.ln2lo);
+    k.shift = opaque_sd(c.shift);
+    k.ln2 = opaque_sd(c.ln2);
 #pragma unroll
     for (int i = 0; i < 10; ++i) k.c[i] = (i == 1) ? opaque_vd(c.c[i]) : opaque_sd(c.c[i]);
     return k;
 }
 
-// Natural logarithm of a positive finite double (NaN otherwise).  With
-// x = m 2^e, m in [1/2, 1), a single-precision estimate l0 of ln m (hardware
-// base-2 logarithm times ln 2, relative error ~1e-7) is corrected exactly:
-// d = m exp(-l0) - 1 is tiny (|d| < 1e-6), ln m = l0 + ln(1 + d), and the
-// series d - d^2/2 + d^3/3 of ln(1 + d) leaves a truncation below d^4/4.
-// The error is that of exp_cw (about 1e-16 absolute); ln 2 is split into a
-// head with trailing zero bits and a tail so that e ln2_hi is exact.  No
-// division and no polynomial table beyond the exponential's.
-__device__ __forceinline__ double log_pos(double x, const ExpK &k) {
+constexpr double LOG2E = 1.44269504088896340736;     // log2(e)
+
+// Base-2 logarithm of a positive finite double (NaN otherwise).  With
+// x = m 2^e, m in [1/2, 1), the hardware single-precision log2 m (relative
+// error ~1e-7) is the estimate l0, corrected exactly: d = m 2^(-l0) - 1 is
+// tiny (|d| < 1e-6), log2 m = l0 + ln(1 + d) log2(e), and the series
+// d - d^2/2 + d^3/3 of ln(1 + d) leaves a truncation below d^4/4.  The error
+// is that of the exponential (about 1e-16 absolute) plus the final rounding.
+// No division and no polynomial table beyond the exponential's.
+__device__ __forceinline__ double log2_pos(double x, const ExpK &k) {
     int e;
     const double m = frexp(x, &e);
-    const double l0 = (double)__builtin_amdgcn_logf((float)m) * 0x1.62e42fefa39efp-1;
-    const double d = __builtin_fma(m, exp_cw(-l0, k), -1.0);
-    const double lm = l0 + d * __builtin_fma(d, __builtin_fma(d, 1.0 / 3.0, -0.5), 1.0);
-    const double ln2_hi = 0x1.62e42fee00000p-1, ln2_lo = 0x1.a39ef35793c76p-33;
-    const double de = (double)e;
-    const double r = __builtin_fma(de, ln2_hi, __builtin_fma(de, ln2_lo, lm));
+    const double l0 = (double)__builtin_amdgcn_logf((float)m);
+    const double d = __builtin_fma(m, exp2_b31(-l0, k), -1.0);
+    const double l1 = d * __builtin_fma(d, __builtin_fma(d, 1.0 / 3.0, -0.5), 1.0);
+    const double r = (double)e + __builtin_fma(l1, LOG2E, l0);
     return (x > 0.0 && x <= 0x1.fffffffffffffp+1023) ? r : __builtin_nan("");
 }
 
-__device__ __forceinline__ double log_pos(double x) { return log_pos(x, exp_k()); }
+__device__ __forceinline__ double log2_pos(double x) { return log2_pos(x, exp_k()); }
 
 // x^(-1/6) for a positive finite x.  With x = m 2^e and e = 6q + t,
 // t in 0..5: x^(-1/6) = a^(-1/6) 2^(-q), a = m 2^t in [1/2, 32).  A
@@ -437,8 +451,8 @@ __device__ __forceinline__ uint32_t opaque_zero() {
     return z;
 }
 
-constexpr double INV_LN10 = 0.43429448190325182765;   // 1 / ln 10
-constexpr double LN10 = 2.30258509299404568402;
+constexpr double LOG10_2 = 0.30102999566398119521;    // log10(2)
+constexpr double LOG2_10 = 3.32192809488736234787;    // log2(10)
 
 // Falloff rate k_inf Pr/(1 + Pr) F with Pr = k_0 [M] / k_inf (Chemkin form);
 // F = 1 (Lindemann) or the Troe factor with log10 F = lFc / (1 + f^2),
@@ -450,9 +464,9 @@ __device__ __forceinline__ double falloff_rate(double kinf, double k0M, double l
     const double Pr = k0M / kinf;
     double F = 1.0;
     if (troe) {
-        const double x = log_pos(Pr, K) * INV_LN10 + (-0.4 - 0.67 * lFc);
+        const double x = log2_pos(Pr, K) * LOG10_2 + (-0.4 - 0.67 * lFc);
         const double f = x / ((0.75 - 1.27 * lFc) - 0.14 * x);
-        F = exp_cw(lFc / (1.0 + f * f) * LN10, K);
+        F = exp2_sat(lFc / (1.0 + f * f) * LOG2_10, K);
     }
     return kinf * (Pr / (1.0 + Pr)) * F;
 }
@@ -544,14 +558,15 @@ __device__ __forceinline__ void rhs_eval(const double (&z)[NSL], double P10, dou
                                          double (&fz)[NSL], const GroupLds &L,
                                          const UnitRegs<RUC> &ur, int g, int N, int RU, int NSEG,
                                          int SEGL, int L2P, int L2N, int RUp, int NMS,
-                                         int RU2) {
+                                         int RU2, double invTmax) {
     constexpr int NK = NSL * G;
     const uint32_t oz = opaque_zero();
     const int go = g + (int)oz;
     const ExpK K = exp_k_local();
     const double T = gbcast0<G>(z[0]);
     const double invT = rcp_nr(T);
-    const double lnT = log_pos(T, K);
+    const double l2T = log2_pos(T, K);
+    const double invTa = fmin(invT, invTmax);   // 1/T of the Arrhenius factors
 
     double sYW = 0.0, sYcp = 0.0;
     double hRT[NSL], invW[NSL];
@@ -617,8 +632,8 @@ __device__ __forceinline__ void rhs_eval(const double (&z)[NSL], double P10, dou
         double q[RUC];
 #pragma unroll
         for (int r = 0; r < RUC; ++r) {
-            const double kf = exp_cw(arrhenius_arg(ur.lnAf[r], ur.bf[r], ur.tf[r], lnT, invT), K);
-            const double kr = exp_cw(arrhenius_arg(ur.lnAr[r], ur.br[r], ur.tr[r], lnT, invT), K);
+            const double kf = exp2_b31(arrhenius_arg(ur.l2Af[r], ur.bf[r], ur.tf[r], l2T, invTa), K);
+            const double kr = exp2_b31(arrhenius_arg(ur.l2Ar[r], ur.br[r], ur.tr[r], l2T, invTa), K);
             const uint32_t a = ur.idf[r] + oz, b = ur.idr[r] + oz;
             // the same operations in the same order as the LDS path below, so
             // the placement of the parameters never changes a result
@@ -656,8 +671,8 @@ __device__ __forceinline__ void rhs_eval(const double (&z)[NSL], double P10, dou
                 cf *= cat(a, 2);
                 cr *= cat(b, 2);
             }
-            const double kf = exp_cw(arrhenius_arg(u0.x, u0.y, u1.x, lnT, invT), K);
-            const double kr = exp_cw(arrhenius_arg(u1.y, u2.x, u2.y, lnT, invT), K);
+            const double kf = exp2_b31(arrhenius_arg(u0.x, u0.y, u1.x, l2T, invTa), K);
+            const double kr = exp2_b31(arrhenius_arg(u1.y, u2.x, u2.y, l2T, invTa), K);
             Q[r * G + g] = net_rate(kf, cf, kr, cr);
             return u3n;
         };
@@ -688,8 +703,8 @@ __device__ __forceinline__ void rhs_eval(const double (&z)[NSL], double P10, dou
             const uint64_t a = __double_as_longlong(u3.x), b = __double_as_longlong(u3.y);
             const double cf = cat(a, 0) * cat(a, 1) * cat(a, 2);
             const double cr = cat(b, 0) * cat(b, 1) * cat(b, 2);
-            double kf = exp_cw(arrhenius_arg(u0.x, u0.y, u1.x, lnT, invT), K);
-            double kr = exp_cw(arrhenius_arg(u1.y, u2.x, u2.y, lnT, invT), K);
+            double kf = exp2_b31(arrhenius_arg(u0.x, u0.y, u1.x, l2T, invTa), K);
+            double kr = exp2_b31(arrhenius_arg(u1.y, u2.x, u2.y, l2T, invTa), K);
             const double2 *pd = reinterpret_cast<const double2 *>(L.pdep) +
                                 (size_t)(6 * (rp - RUp)) * G + g;
             const double2 d0 = pd[0];
@@ -702,15 +717,17 @@ __device__ __forceinline__ void rhs_eval(const double (&z)[NSL], double P10, dou
                     kr *= M;
                 } else {
                     const double2 d1 = pd[G], d2 = pd[2 * G], d3 = pd[3 * G];
-                    const double k0f = exp_cw(arrhenius_arg(d0.y, d1.x, d1.y, lnT, invT), K);
-                    const double k0r = exp_cw(arrhenius_arg(d2.x, d2.y, d3.x, lnT, invT), K);
+                    const double k0f = exp2_b31(arrhenius_arg(d0.y, d1.x, d1.y, l2T, invTa), K);
+                    const double k0r = exp2_b31(arrhenius_arg(d2.x, d2.y, d3.x, l2T, invTa), K);
                     double lFc = 0.0;   // log10 of the Troe centre value (Lindemann: F = 1)
                     if (kind == 3) {
                         const double2 d4 = pd[4 * G], d5 = pd[5 * G];
-                        const double Fc = (1.0 - d4.x) * exp_cw(-T * d4.y, K) +
-                                          d4.x * exp_cw(-T * d5.x, K) +
-                                          (d5.y > 0.0 ? exp_cw(-d5.y * invT, K) : 0.0);
-                        lFc = log_pos(Fc, K) * INV_LN10;
+                        // exp(-T/T***), exp(-T/T*), exp(-T**/T) in base 2
+                        // (the host stores log2(e)/T***, log2(e)/T*, T** log2(e))
+                        const double Fc = (1.0 - d4.x) * exp2_sat(-T * d4.y, K) +
+                                          d4.x * exp2_sat(-T * d5.x, K) +
+                                          (d5.y > 0.0 ? exp2_sat(-d5.y * invT, K) : 0.0);
+                        lFc = log2_pos(Fc, K) * LOG10_2;
                     }
                     kf = falloff_rate(kf, k0f * M, lFc, kind == 3, K);
                     kr = falloff_rate(kr, k0r * M, lFc, kind == 3, K);
@@ -785,8 +802,8 @@ __device__ __forceinline__ void load_unit_regs(const Params &p, UnitRegs<RUC> &u
 #pragma unroll
         for (int r = 0; r < RUC; ++r) {
             const double *u = p.tab.units + (size_t)(r * G + g) * UNIT_DOUBLES;
-            ur.lnAf[r] = u[0]; ur.bf[r] = u[1]; ur.tf[r] = u[2];
-            ur.lnAr[r] = u[3]; ur.br[r] = u[4]; ur.tr[r] = u[5];
+            ur.l2Af[r] = u[0]; ur.bf[r] = u[1]; ur.tf[r] = u[2];
+            ur.l2Ar[r] = u[3]; ur.br[r] = u[4]; ur.tr[r] = u[5];
             // 16-bit byte offsets -> three 10-bit indices
             const uint64_t bf = __double_as_longlong(u[6]), br = __double_as_longlong(u[7]);
             uint32_t f = 0, v = 0;
@@ -956,7 +973,7 @@ __global__ __launch_bounds__((Occ<RUC, NSL>::threads), (Occ<RUC, NSL>::waves)) v
     if (!active) z[0] = (g == 0) ? 1000.0 : z[0];
     const double P10 = active ? p.P[cell] * 10.0 : 1e6;
     rhs_eval<G, NSL, RUC, PD>(z, P10, 1.0 / P10, fz, L, ur, g, p.N, p.RU, p.NSEG, p.SEGL, p.L2P,
-                              p.L2N, p.RUp, p.NMS, p.RU2);
+                              p.L2N, p.RUp, p.NMS, p.RU2, p.invTmax);
     if (active) {
 #pragma unroll
         for (int s = 0; s < NSL; ++s) {

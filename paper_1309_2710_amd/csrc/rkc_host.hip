@@ -1,6 +1,7 @@
 // Host runtime of the C ABI declared in include/rkc.h: mechanism packing and
 // upload, variant selection, launch configuration and host<->device staging.
 #include <algorithm>
+#include <cfloat>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -19,8 +20,10 @@ namespace {
 
 constexpr double R_J = 8.31446261815324;   // J/(mol K)
 using rkchost::AGG_N;
-constexpr double LNA_ZERO = -1e4;          // ln A of a reaction whose rate is identically 0
-constexpr double TROE_BOUND = 1e10;        // largest 1/T***, 1/T* and T** passed to the kernels
+constexpr double L2A_ZERO = -1e4;          // log2 A of a reaction whose rate is identically 0
+constexpr double TROE_BOUND = 1e10;        // largest log2(e)/T***, log2(e)/T* and T** log2(e)
+                                           // passed to the kernels
+constexpr long double LOG2E_L = 1.442695040888963407359924681001892137L;
 
 // Device tables that depend on the lane-group shape: the species table is
 // laid out with stride NK, the gather is balanced over G lanes.
@@ -52,6 +55,7 @@ struct rkc_mech {
     std::vector<double> units_h;                       // [nU_pad][8]
     int n_plain = 0, n_pdep = 0;                       // units [0, n_plain) plain, then pdep
     int n_two = 0;   // units [0, n_two) plain with at most two reactant slots per side
+    double invTmax = 0.0;   // bound on 1/T in the Arrhenius factors (see rkc_mech_create)
     std::vector<double> pdep_h;                        // [n_pdep][PDEP_DOUBLES]
     std::vector<std::vector<double>> effsets;          // distinct efficiency vectors [nS]
     double *pdep_d = nullptr;
@@ -107,7 +111,10 @@ uint64_t pack_slots(const int32_t *slots, int nS) {
     return v;
 }
 
-double ln_a(double A) { return A > 0.0 ? std::log(A) : LNA_ZERO; }
+// The kernels evaluate rate constants in base 2 (2^(log2 A + beta log2 T -
+// theta'/T)): log2 A and theta' = (Ea/R) log2(e), each rounded once.
+double l2_a(double A) { return A > 0.0 ? (double)std::log2((long double)A) : L2A_ZERO; }
+double theta2(double Ea) { return (double)((long double)Ea / (long double)R_J * LOG2E_L); }
 
 // Stage counts whose RKC coefficients are tabulated (larger ones are computed
 // by the kernels' recurrences).
@@ -715,6 +722,7 @@ void fill_params(const rkc_mech *m, const Choice &ch, const NkTables *nk, rkcdev
         p->l_pdep = m->pdep_d;
         p->l_eff = m->l_eff_d;
         p->lane_rows = lane_rows(m);
+        p->invTmax = m->invTmax;
         p->agg = m->agg_d;
         p->queue = m->queue_d;
         p->coef = m->coef_d;
@@ -738,6 +746,7 @@ void fill_params(const rkc_mech *m, const Choice &ch, const NkTables *nk, rkcdev
     p->tab.eff = nk->eff;
     p->RUp = nk->RUp;
     p->RU2 = nk->RU2;
+    p->invTmax = m->invTmax;
     p->NPR = nk->NPR;
     p->NMS = nk->NMS;
     p->agg = m->agg_d;
@@ -954,8 +963,8 @@ int rkc_mech_create(const rkc_mech_desc *d, rkc_mech **out) {
                     return RKC_EINVAL;
         if (kind >= RKC_PDEP_LINDEMANN) {
             if (!d->A0 || !d->beta0 || !d->Ea0) return RKC_EINVAL;
-            if (!(d->A0[j] >= 0.0) || !std::isfinite(d->A0[j]) || !std::isfinite(d->beta0[j]) ||
-                !std::isfinite(d->Ea0[j]))
+            if (!(d->A0[j] >= 0.0) || !std::isfinite(d->A0[j]) ||
+                !(std::fabs(d->beta0[j]) <= 1e5) || !std::isfinite(d->Ea0[j]))
                 return RKC_EINVAL;
         }
         if (kind == RKC_PDEP_TROE) {
@@ -966,7 +975,7 @@ int rkc_mech_create(const rkc_mech_desc *d, rkc_mech **out) {
         }
     }
     for (int j = 0; j < nR; ++j) {
-        if (!(d->A[j] >= 0.0) || !std::isfinite(d->A[j]) || !std::isfinite(d->beta[j]) ||
+        if (!(d->A[j] >= 0.0) || !std::isfinite(d->A[j]) || !(std::fabs(d->beta[j]) <= 1e5) ||
             !std::isfinite(d->Ea[j]))
             return RKC_EINVAL;
         for (int s = 0; s < 3; ++s) {
@@ -1017,18 +1026,18 @@ int rkc_mech_create(const rkc_mech_desc *d, rkc_mech **out) {
         std::memset(u.rec, 0, sizeof(u.rec));
         std::memset(u.pd, 0, sizeof(u.pd));
         u.kind = kind;
-        u.rec[0] = ln_a(d->A[j]);
+        u.rec[0] = l2_a(d->A[j]);
         u.rec[1] = d->beta[j];
-        u.rec[2] = d->Ea[j] / R_J;
+        u.rec[2] = theta2(d->Ea[j]);
         uint64_t idr = 0;
         const int32_t none[3] = {-1, -1, -1};
         if (pair) {
-            u.rec[3] = ln_a(d->A[j + 1]);
+            u.rec[3] = l2_a(d->A[j + 1]);
             u.rec[4] = d->beta[j + 1];
-            u.rec[5] = d->Ea[j + 1] / R_J;
+            u.rec[5] = theta2(d->Ea[j + 1]);
             idr = pack_slots(d->reac + 3 * (j + 1), nS);
         } else {
-            u.rec[3] = LNA_ZERO;
+            u.rec[3] = L2A_ZERO;
             idr = pack_slots(none, nS);
         }
         auto n_slots = [](const int32_t *x) { return (x[0] >= 0) + (x[1] >= 0) + (x[2] >= 0); };
@@ -1045,25 +1054,25 @@ int rkc_mech_create(const rkc_mech_desc *d, rkc_mech **out) {
             const uint64_t tag = (uint64_t)kind | ((uint64_t)q << 8);
             std::memcpy(&u.pd[0], &tag, 8);
             if (kind >= RKC_PDEP_LINDEMANN) {
-                u.pd[1] = ln_a(d->A0[j]);
+                u.pd[1] = l2_a(d->A0[j]);
                 u.pd[2] = d->beta0[j];
-                u.pd[3] = d->Ea0[j] / R_J;
-                u.pd[4] = pair ? ln_a(d->A0[j + 1]) : LNA_ZERO;
+                u.pd[3] = theta2(d->Ea0[j]);
+                u.pd[4] = pair ? l2_a(d->A0[j + 1]) : L2A_ZERO;
                 u.pd[5] = pair ? d->beta0[j + 1] : 0.0;
-                u.pd[6] = pair ? d->Ea0[j + 1] / R_J : 0.0;
+                u.pd[6] = pair ? theta2(d->Ea0[j + 1]) : 0.0;
             }
             if (kind == RKC_PDEP_TROE) {
                 const double *t = d->troe + 4 * (size_t)j;
                 // The kernels evaluate exp(-T / T***), exp(-T / T*) and
-                // exp(-T** / T) with an exponential exact for arguments of
-                // magnitude below 1e16.  Sentinels such as T*** = 1e-30 or
-                // T** = 1e30 ("term off") are bounded to TROE_BOUND, which
-                // leaves every value unchanged between 1e-6 K and 1e6 K: the
-                // term is exactly 0 there either way.
+                // exp(-T** / T) as powers of 2 with a saturating exponential
+                // exact for arguments of magnitude below 2^51.  Sentinels
+                // such as T*** = 1e-30 or T** = 1e30 ("term off") are bounded
+                // to TROE_BOUND, which leaves every value unchanged between
+                // 1e-5 K and 1e5 K: the term is exactly 0 there either way.
                 u.pd[8] = t[0];
-                u.pd[9] = std::min(1.0 / t[1], TROE_BOUND);
-                u.pd[10] = std::min(1.0 / t[2], TROE_BOUND);
-                u.pd[11] = std::min(t[3], TROE_BOUND);
+                u.pd[9] = std::min((double)(LOG2E_L / t[1]), TROE_BOUND);
+                u.pd[10] = std::min((double)(LOG2E_L / t[2]), TROE_BOUND);
+                u.pd[11] = std::min((double)(t[3] * LOG2E_L), TROE_BOUND);
             }
         }
         for (int i = 0; i < nS; ++i) {
@@ -1072,6 +1081,28 @@ int rkc_mech_create(const rkc_mech_desc *d, rkc_mech **out) {
         }
         srcs.push_back(u);
         j += pair ? 2 : 1;
+    }
+    // Bound on the 1/T of the Arrhenius factors that keeps every base-2
+    // exponent |log2 A + beta log2 T - theta' / T| below 2^30 (|log2 T| <= 1075
+    // for a positive double), as the kernels' exponential needs; with
+    // |beta| <= 1e5 the numerator stays above 2^29.
+    {
+        double amax = 0.0, bmax = 0.0, tmax = 0.0;
+        auto arr = [&](const double *x) {
+            amax = std::max(amax, std::fabs(x[0]));
+            bmax = std::max(bmax, std::fabs(x[1]));
+            tmax = std::max(tmax, std::fabs(x[2]));
+        };
+        for (const UnitSrc &u : srcs) {
+            arr(u.rec);
+            arr(u.rec + 3);
+            if (u.kind >= RKC_PDEP_LINDEMANN) {
+                arr(u.pd + 1);
+                arr(u.pd + 4);
+            }
+        }
+        const double num = 1073741824.0 - amax - 1075.0 * bmax;
+        m->invTmax = tmax > 0.0 ? num / tmax : DBL_MAX;
     }
     // plain units with at most two reactant slots on each side first: whole
     // rounds of them skip the third concentration factor (always the 1.0 slot)

@@ -262,7 +262,7 @@ __global__ __launch_bounds__((Occ<RUC, NSL>::threads), (Occ<RUC, NSL>::waves)) v
         {
             ParamsK &pr = *params_k();
             rhs_eval<G, NSL, RUC, PD>(z, S.P10, S.invP10, fz, L, ur, g, N, pr.RU, pr.NSEG, pr.SEGL,
-                                      pr.L2P, pr.L2N, pr.RUp, pr.NMS, pr.RU2);
+                                      pr.L2P, pr.L2N, pr.RUp, pr.NMS, pr.RU2, pr.invTmax);
         }
         if (S.cell >= 0) {
             ParamsK &pk = *params_k();
@@ -631,7 +631,7 @@ __global__ __launch_bounds__((Occ<RUC, NSL>::threads), (Occ<RUC, NSL>::waves)) v
         if (!__any(S.cell >= 0)) break;   // a wave whose groups hold no cell issues nothing
         ++iters;
         rhs_eval<G, NSL, RUC, PD>(z, S.P10, S.invP10, fz, L, ur, g, N, p.RU, p.NSEG, p.SEGL,
-                                  p.L2P, p.L2N, p.RUp, p.NMS, p.RU2);
+                                  p.L2P, p.L2N, p.RUp, p.NMS, p.RU2, p.invTmax);
         if (S.cell >= 0) {
             Counts c = S.c;
             c.n_rhs += 1;
@@ -705,13 +705,13 @@ __global__ __launch_bounds__((Occ<RUC, NSL>::threads), (Occ<RUC, NSL>::waves)) v
                         fin = ST_OK;
                     } else {
                         S.t = S.t + h;
-                        double fac = (errmax == 0.0) ? 5.0 : 0.9 * exp_cw(-0.2 * log_pos(errmax));
+                        double fac = (errmax == 0.0) ? 5.0 : 0.9 * exp2_sat(-0.2 * log2_pos(errmax));
                         if (fac > 5.0) fac = 5.0;
                         hn = h * fac;
                     }
                 } else {
                     c.n_reject += 1;
-                    double fac = isfinite(errmax) ? 0.9 * exp_cw(-0.25 * log_pos(errmax)) : 0.1;
+                    double fac = isfinite(errmax) ? 0.9 * exp2_sat(-0.25 * log2_pos(errmax)) : 0.1;
                     if (fac < 0.1) fac = 0.1;
                     hn = h * fac;
                 }

@@ -72,7 +72,7 @@ __host__ __device__ inline int lane_row_mset(int nS) { return 2 * nS + 2; }
 
 // Unit record of the lane kernels: LU_DOUBLES doubles (two 64-byte scalar
 // loads).
-//   [0..7]   as the lane-group unit record (ln A, beta, theta forward and
+//   [0..7]   as the lane-group unit record (log2 A, beta, theta' forward and
 //            reverse; forward and reverse reactant slots as 16-bit byte
 //            offsets k * 8, the empty slot at n_species * 8, i.e. the row
 //            of ones)
@@ -85,14 +85,14 @@ constexpr int LU_TERMS = 6;
 
 // A unit record in scalar registers.
 struct LaneUnit {
-    double lnAf, bf, tf, lnAr, br, tr;
+    double l2Af, bf, tf, l2Ar, br, tr;
     uint64_t sf, sr, t03, t45;
     double dnu[LU_TERMS];
 };
 
 __device__ __forceinline__ LaneUnit lane_unit(cdouble *r) {
     LaneUnit u;
-    u.lnAf = r[0]; u.bf = r[1]; u.tf = r[2]; u.lnAr = r[3]; u.br = r[4]; u.tr = r[5];
+    u.l2Af = r[0]; u.bf = r[1]; u.tf = r[2]; u.l2Ar = r[3]; u.br = r[4]; u.tr = r[5];
     u.sf = __double_as_longlong(r[6]);
     u.sr = __double_as_longlong(r[7]);
     u.t03 = __double_as_longlong(r[8]);
@@ -126,7 +126,8 @@ __device__ __forceinline__ void rhs_lane(const double (&z)[NMAX], double P10, do
     cdouble *spec = cptr(pk.l_spec);
     const double T = z[0];
     const double invT = rcp_nr(T);
-    const double lnT = log_pos(T, K);
+    const double l2T = log2_pos(T, K);
+    const double invTa = fmin(invT, pk.invTmax);   // 1/T of the Arrhenius factors
     const uint32_t orow0 = (uint32_t)lane_row_omega(nS) * LROW;
 
     // mixture sums (E:mass): sum Y/W and sum (Y/W) Cp/R
@@ -186,8 +187,8 @@ __device__ __forceinline__ void rhs_lane(const double (&z)[NMAX], double P10, do
         for (int t = 0; t < LU_TERMS; ++t) om[t] = lrow_at(lb, term_off(cu, t));
         // the next unit's record (the last unit reloads its own)
         un = lane_unit(units + (size_t)(u + 1 < nU ? u + 1 : u) * LU_DOUBLES);
-        double kf = exp_cw(arrhenius_arg(cu.lnAf, cu.bf, cu.tf, lnT, invT), K);
-        double kr = exp_cw(arrhenius_arg(cu.lnAr, cu.br, cu.tr, lnT, invT), K);
+        double kf = exp2_b31(arrhenius_arg(cu.l2Af, cu.bf, cu.tf, l2T, invTa), K);
+        double kr = exp2_b31(arrhenius_arg(cu.l2Ar, cu.br, cu.tr, l2T, invTa), K);
         if (PD && u >= n_plain) {
             cdouble *d = cptr(pk.l_pdep) + (size_t)(u - n_plain) * PDEP_DOUBLES;
             const uint64_t tag = __double_as_longlong(d[0]);
@@ -198,14 +199,14 @@ __device__ __forceinline__ void rhs_lane(const double (&z)[NMAX], double P10, do
                     kf *= M;
                     kr *= M;
                 } else {
-                    const double k0f = exp_cw(arrhenius_arg(d[1], d[2], d[3], lnT, invT), K);
-                    const double k0r = exp_cw(arrhenius_arg(d[4], d[5], d[6], lnT, invT), K);
+                    const double k0f = exp2_b31(arrhenius_arg(d[1], d[2], d[3], l2T, invTa), K);
+                    const double k0r = exp2_b31(arrhenius_arg(d[4], d[5], d[6], l2T, invTa), K);
                     double lFc = 0.0;
                     if (kind == 3) {
-                        const double Fc = (1.0 - d[8]) * exp_cw(-T * d[9], K) +
-                                          d[8] * exp_cw(-T * d[10], K) +
-                                          (d[11] > 0.0 ? exp_cw(-d[11] * invT, K) : 0.0);
-                        lFc = log_pos(Fc, K) * INV_LN10;
+                        const double Fc = (1.0 - d[8]) * exp2_sat(-T * d[9], K) +
+                                          d[8] * exp2_sat(-T * d[10], K) +
+                                          (d[11] > 0.0 ? exp2_sat(-d[11] * invT, K) : 0.0);
+                        lFc = log2_pos(Fc, K) * LOG10_2;
                     }
                     kf = falloff_rate(kf, k0f * M, lFc, kind == 3, K);
                     kr = falloff_rate(kr, k0r * M, lFc, kind == 3, K);
@@ -899,13 +900,13 @@ __global__ __launch_bounds__(256) void rkck_lane_kernel(Params p) {
                         f = ST_OK;
                     } else {
                         t = t + h;
-                        double fac = (errmax == 0.0) ? 5.0 : 0.9 * exp_cw(-0.2 * log_pos(errmax));
+                        double fac = (errmax == 0.0) ? 5.0 : 0.9 * exp2_sat(-0.2 * log2_pos(errmax));
                         if (fac > 5.0) fac = 5.0;
                         hn = h * fac;
                     }
                 } else {
                     c.n_reject += 1;
-                    double fac = isfinite(errmax) ? 0.9 * exp_cw(-0.25 * log_pos(errmax)) : 0.1;
+                    double fac = isfinite(errmax) ? 0.9 * exp2_sat(-0.25 * log2_pos(errmax)) : 0.1;
                     if (fac < 0.1) fac = 0.1;
                     hn = h * fac;
                 }
