@@ -70,6 +70,12 @@ def test_mech_create_rejects_bad_descriptions_without_a_device():
     assert _create(m, A=a) == rkc.EINVAL
     e = np.array(m["Ea"]); e[3] = np.nan
     assert _create(m, Ea=e) == rkc.EINVAL
+    # temperature exponents beyond 1e5 in magnitude (the kernels bound 1/T in
+    # the Arrhenius factors by a value that needs |beta| <= 1e5)
+    b = np.array(m["beta"]); b[4] = 2e5
+    assert _create(m, beta=b) == rkc.EINVAL
+    b = np.array(m["beta"]); b[4] = -np.inf
+    assert _create(m, beta=b) == rkc.EINVAL
     d = rkc.MechDesc(1022, 0, *[None] * 9)
     assert L.rkc_mech_create(ct.byref(d), ct.byref(h)) == rkc.ENOTSUP
     d = rkc.MechDesc(0, 0, *[None] * 9)

@@ -57,6 +57,38 @@ def test_rhs_parity(R, cfg, G):
     assert eT.max() <= 1e-11
 
 
+# Temperatures far outside the workloads' range drive the Arrhenius exponents
+# (base 2) from deep underflow (about -3000 at 50 K) to near overflow (+800
+# for reverse rates with negative activation temperature at 50 K) and past it
+# (20 K: the oracle's rates overflow to inf).
+EXTREME_T = [50.0, 100.0, 300.0, 5000.0, 2e4, 1e5]
+
+
+@pytest.mark.parametrize("cfg,G", [("c2", 16), ("c2", 1), ("c3", 64), ("c4p", 0)])
+def test_rhs_parity_extreme_temperatures(R, cfg, G):
+    _say("rhs extreme T", cfg, "G", G)
+    gm, om = mech(R, cfg)
+    st = synth.config_states(cfg, 8)
+    n = len(st["T"])
+    T = np.repeat(np.array(EXTREME_T), n)
+    P = np.tile(st["P"], len(EXTREME_T))
+    Y = np.tile(st["Y"], (len(EXTREME_T), 1))
+    fg = R.rhs(gm, T, P, Y, lanes_per_cell=G)
+    fo = om.rhs(T, P, Y)
+    assert np.isfinite(fo).all()
+    scale = np.abs(fo[:, 1:]).max(axis=1, keepdims=True)
+    eY = np.abs(fg[:, 1:] - fo[:, 1:]) / scale
+    eT = np.abs(fg[:, 0] - fo[:, 0]) / np.abs(fo[:, 0])
+    _say("max eY", eY.max(), "max eT", eT.max(), "scales", scale.min(), scale.max())
+    assert eY.max() <= 1e-12
+    assert eT.max() <= 1e-11
+    # 20 K: rates overflow on both sides, the same cells are non-finite
+    T20 = np.full(n, 20.0)
+    fg20 = R.rhs(gm, T20, st["P"], st["Y"], lanes_per_cell=G)
+    fo20 = om.rhs(T20, st["P"], st["Y"])
+    assert (np.isfinite(fg20).all(axis=1) == np.isfinite(fo20).all(axis=1)).all()
+
+
 max_flips = PT.max_flips
 
 
