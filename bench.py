@@ -29,7 +29,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6        # MI355X FP64 vector: 256 CU x 128 flop/clk x 2.4 GHz
-EXP_FLOPS = 27                 # FP64 arithmetic of one device exp: 1 MUL + 2 FMA + 11 FMA
+EXP_FLOPS = 25                 # FP64 arithmetic of one device exponential (2^y): 3 ADD for
+                               # y = n + f, 11 FMA for the polynomial
 METRIC = "cell-ODEs integrated per sec over dt (53sp/634rx, FP64); p99 batch latency"
 
 
@@ -60,7 +61,7 @@ def rhs_flops(mech):
     return f + pdep_flops(mech)
 
 
-LOG_FLOPS = EXP_FLOPS           # a natural logarithm counted like an exponential
+LOG_FLOPS = EXP_FLOPS           # a logarithm counted like an exponential
 
 
 def pdep_flops(mech):
@@ -73,7 +74,7 @@ def pdep_flops(mech):
     5.  Troe adds the centre value (three exponentials with their arguments
     and the sum, 3 exp + 7), its log10 (log + 1), c and n (4), and per
     direction log10 Pr (log + 1), x, f = x / (n - 0.14 x), 1 + f^2, the
-    quotient, the scaling to a natural exponent (8) and exp (exp + 1 for the
+    quotient, the scaling to a base-2 exponent (8) and exp (exp + 1 for the
     product with the Lindemann rate)."""
     if mech.get("pdep") is None:
         return 0
