@@ -82,11 +82,15 @@ def test_rhs_parity_extreme_temperatures(R, cfg, G):
     _say("max eY", eY.max(), "max eT", eT.max(), "scales", scale.min(), scale.max())
     assert eY.max() <= 1e-12
     assert eT.max() <= 1e-11
-    # 20 K: rates overflow on both sides, the same cells are non-finite
-    T20 = np.full(n, 20.0)
-    fg20 = R.rhs(gm, T20, st["P"], st["Y"], lanes_per_cell=G)
-    fo20 = om.rhs(T20, st["P"], st["Y"])
-    assert (np.isfinite(fg20).all(axis=1) == np.isfinite(fo20).all(axis=1)).all()
+    # 20 K: rates overflow on both sides, the same cells are non-finite; far
+    # below, down to the smallest subnormal, where the kernels bound 1/T in
+    # the Arrhenius factors, every cell stays non-finite on both sides (no
+    # finite value from a wrapped exponent)
+    for Tlow in (20.0, 1e-3, 1e-6, 1e-300, 5e-324):
+        Tl = np.full(n, Tlow)
+        fgl = R.rhs(gm, Tl, st["P"], st["Y"], lanes_per_cell=G)
+        fol = om.rhs(Tl, st["P"], st["Y"])
+        assert (np.isfinite(fgl).all(axis=1) == np.isfinite(fol).all(axis=1)).all(), Tlow
 
 
 max_flips = PT.max_flips
