@@ -679,6 +679,44 @@ __device__ __forceinline__ void rhs_eval(const double (&z)[NSL], double P10, dou
         const std::integral_constant<bool, false> two_slots;
         const std::integral_constant<bool, true> three_slots;
         const int r_fast = PD ? RUp : RU;
+        if constexpr (RUC < 0 && !PD) {
+            // records in global memory: the whole record of the next unit is
+            // loaded before this unit is computed, so the cache latency runs
+            // under a unit's arithmetic (the table ends with a zero round)
+            struct Rec {
+                double2 a, b, c, d;
+            };
+            auto load = [&](int r) {
+                const double2 *u = ub + (size_t)(4 * r) * G;
+                return Rec{u[0], u[G], u[2 * G], u[3 * G]};
+            };
+            auto unitg = [&](int r, const Rec cur, auto three) {
+                const Rec nxt = load(r + 1);
+                const uint64_t a = __double_as_longlong(cur.d.x), b = __double_as_longlong(cur.d.y);
+                double cf = cat(a, 0) * cat(a, 1);
+                double cr = cat(b, 0) * cat(b, 1);
+                if constexpr (decltype(three)::value) {
+                    cf *= cat(a, 2);
+                    cr *= cat(b, 2);
+                }
+                const double kf = exp2_b31(arrhenius_arg(cur.a.x, cur.a.y, cur.b.x, l2T, invTa), K);
+                const double kr = exp2_b31(arrhenius_arg(cur.b.y, cur.c.x, cur.c.y, l2T, invTa), K);
+                Q[r * G + g] = net_rate(kf, cf, kr, cr);
+                return nxt;
+            };
+            Rec ra = load(0);
+            int r = 0;
+            for (; r + 1 < RU2; r += 2) {
+                const Rec rb = unitg(r, ra, two_slots);
+                ra = unitg(r + 1, rb, two_slots);
+            }
+            if (r < RU2) ra = unitg(r++, ra, two_slots);
+            for (; r + 1 < r_fast; r += 2) {
+                const Rec rb = unitg(r, ra, three_slots);
+                ra = unitg(r + 1, rb, three_slots);
+            }
+            if (r < r_fast) (void)unitg(r, ra, three_slots);
+        } else {
         // two units per iteration, so that the prefetched slots alternate
         // between two registers instead of being copied every unit
         double2 u3a = ub[3 * G];
@@ -693,6 +731,7 @@ __device__ __forceinline__ void rhs_eval(const double (&z)[NSL], double P10, dou
             u3a = unit(r + 1, u3b, three_slots);
         }
         if (r < r_fast) (void)unit(r, u3a, three_slots);
+        }
         // rounds with pressure-dependent units: third body and falloff (only
         // in the kernels built for mechanisms that have them)
         if constexpr (PD)
