@@ -679,7 +679,7 @@ __device__ __forceinline__ void rhs_eval(const double (&z)[NSL], double P10, dou
         const std::integral_constant<bool, false> two_slots;
         const std::integral_constant<bool, true> three_slots;
         const int r_fast = PD ? RUp : RU;
-        if constexpr (RUC < 0 && !PD) {
+        if constexpr (RUC < 0) {
             // records in global memory: the whole record of the next unit is
             // loaded before this unit is computed, so the cache latency runs
             // under a unit's arithmetic (the table ends with a zero round)
