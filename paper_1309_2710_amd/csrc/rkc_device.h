@@ -275,6 +275,7 @@ struct UnitRegs<-1> {};
 
 struct GroupLds {
     const double *spec;
+    const double *tmid;    // [NK] range switch temperatures (LDS in every variant)
     const uint32_t *gather;
     const uint32_t *gather2;
     const double *units;   // interleaved records: LDS (RUC == 0) or global (RUC == -1)
@@ -575,7 +576,7 @@ __device__ __forceinline__ void rhs_eval(const double (&z)[NSL], double P10, dou
         const int k = s * G + go;
         const double Y = (k == 0) ? 0.0 : z[s];
         invW[s] = L.spec[F_INVW * NK + k];
-        const bool hi = T >= L.spec[F_TMID * NK + k];
+        const bool hi = T >= L.tmid[k];
         const double *a = L.spec + (hi ? F_CPHI : F_CPLO) * NK + k;
         const double *b = L.spec + (hi ? F_HHI : F_HLO) * NK + k;
         const double cpR = a[0] + T * (a[NK] + T * (a[2 * NK] + T * (a[3 * NK] + T * a[4 * NK])));
@@ -880,9 +881,11 @@ __host__ __device__ inline size_t group_doubles(const Shape &s) {
            (size_t)((s.NMS + 1) & ~1);
 }
 
-// Bytes of dynamic LDS for a workgroup of `groups` groups.
+// Bytes of dynamic LDS for a workgroup of `groups` groups.  With the species
+// table in global memory its T_mid row is still staged, so that choosing a
+// NASA range does not wait for a global load before the coefficient loads.
 __host__ __device__ inline size_t lds_bytes(const Shape &s, int groups) {
-    size_t b = s.spec_in_lds ? (size_t)NFIELD * s.NK * 8 : 0;
+    size_t b = (size_t)(s.spec_in_lds ? NFIELD : 1) * s.NK * 8;
     if (s.units_in_lds) b += (size_t)s.RU * s.G * UNIT_DOUBLES * 8;
     b += (size_t)s.NPR * s.G * PDEP_DOUBLES * 8;
     b += (size_t)s.NMS * s.NK * 8;
@@ -903,7 +906,7 @@ __device__ __forceinline__ LdsPtrs carve(unsigned char *base, const Shape &s, in
     LdsPtrs l;
     size_t off = 0;
     l.spec = reinterpret_cast<double *>(base + off);
-    if (s.spec_in_lds) off += (size_t)NFIELD * s.NK * 8;
+    off += (size_t)(s.spec_in_lds ? NFIELD : 1) * s.NK * 8;
     l.units = reinterpret_cast<double *>(base + off);
     if (s.units_in_lds) off += (size_t)s.RU * s.G * UNIT_DOUBLES * 8;
     l.pdep = reinterpret_cast<double *>(base + off); off += (size_t)s.NPR * s.G * PDEP_DOUBLES * 8;
@@ -922,6 +925,7 @@ __device__ __forceinline__ LdsPtrs carve(unsigned char *base, const Shape &s, in
 __device__ __forceinline__ GroupLds group_view(const LdsPtrs &lp, const Shape &s, int gib) {
     GroupLds L;
     L.spec = lp.spec; L.gather = lp.gather; L.gather2 = lp.gather2;
+    L.tmid = s.spec_in_lds ? lp.spec + F_TMID * s.NK : lp.spec;
     L.units = lp.units;
     L.pdep = lp.pdep;
     L.eff = lp.eff;
@@ -942,6 +946,8 @@ __device__ __forceinline__ void stage_tables(const Params &p, int G, const LdsPt
     for (int i = tid; i < p.NMS * p.NK; i += nt) lp.eff[i] = p.tab.eff[i];
     if (spec_l)
         for (int i = tid; i < NFIELD * p.NK; i += nt) spec_lp[i] = p.tab.spec[i];
+    else
+        for (int i = tid; i < p.NK; i += nt) spec_lp[i] = p.tab.spec[F_TMID * p.NK + i];
     for (int i = tid; i < p.NSEG * (p.SEGL / 2) * G; i += nt) gather_l[i] = p.tab.gather[i];
     for (int i = tid; i < p.NK * ((p.L2P + p.L2N) / 2); i += nt) lp.gather2[i] = p.tab.gather2[i];
     // unit records, lane-interleaved in 16-byte pieces (see rhs_eval)
