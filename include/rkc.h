@@ -73,7 +73,8 @@ extern "C" {
                                     is compiled (else LDS) */
 #define RKC_PARAMS_LDS        2
 #define RKC_PARAMS_GLOBAL     3  /* reaction parameters and species table read from
-                                    global memory through the caches; RKC_ENOTSUP
+                                    global memory through the caches (the range
+                                    switch temperatures staged in LDS); RKC_ENOTSUP
                                     when no such variant is compiled for the shape */
 
 /* Largest n_cells of one call (2^31 - 2^20): cell indices and work-queue
