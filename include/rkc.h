@@ -62,7 +62,9 @@ extern "C" {
 /* ---- launch schedule (never changes results: see rkc_integrate) --------- */
 #define RKC_SCHED_AUTO        0
 #define RKC_SCHED_PLAIN       1  /* one lane group per cell, grid covers all cells */
-#define RKC_SCHED_PERSISTENT  2  /* resident grid; groups pull cells from a device queue */
+#define RKC_SCHED_PERSISTENT  2  /* resident grid; groups pull cells from a device queue
+                                    in index order (cells ordered by decreasing expected
+                                    cost, e.g. temperature, shorten the final tail) */
 
 /* ---- placement of reaction parameters (never changes results) --------- */
 #define RKC_PARAMS_AUTO       0  /* LDS (the measured faster placement), or global
