@@ -1,7 +1,8 @@
 """The allocation-free entry point (rkc_integrate_device_noalloc) against
 rkc_integrate with the same options: bitwise equal states, statuses and
 per-cell counters, on two calls in a row (the second smaller), for the
-lane-group and the one-lane-per-cell kernels and both methods; refusal before
+lane-group kernels (parameters in LDS and in global memory) and the
+one-lane-per-cell kernels, and both methods; refusal before
 the tables exist, for host arrays and above the size limit."""
 import ctypes as ct
 
@@ -33,7 +34,10 @@ def _dev(st, n, layout=0):
             torch.from_numpy(np.ascontiguousarray(Y)).to(d))
 
 
-CASES = [("c1", 0, 0, 0), ("c2", 16, 0, 0), ("c2", 1, 1, 0), ("c1", 16, 0, 1)]
+# the 111-species sets run the kernels that read the reaction records from
+# global memory (plain and with third-body and falloff rounds)
+CASES = [("c1", 0, 0, 0), ("c2", 16, 0, 0), ("c2", 1, 1, 0), ("c1", 16, 0, 1), ("c4", 0, 0, 0),
+         ("c4p", 0, 0, 0)]
 
 
 @pytest.mark.parametrize("cfg,lanes,layout,method", CASES)
