@@ -93,6 +93,43 @@ def test_rhs_parity_extreme_temperatures(R, cfg, G):
         assert (np.isfinite(fgl).all(axis=1) == np.isfinite(fol).all(axis=1)).all(), Tlow
 
 
+def _range_switch_mech(cfg):
+    """The set's mechanism with a distinct NASA switch temperature per species
+    and a high range that differs from the low one (Cp/R and H/(R T) offset),
+    so that choosing the wrong range shows in the source term."""
+    m = dict(synth.config_mechanism(cfg))
+    nS = m["n_species"]
+    m["T_mid"] = 900.0 + 7.0 * np.arange(nS)
+    hi = np.array(m["nasa_high"], dtype=np.float64).reshape(nS, 7).copy()
+    hi[:, 0] *= 1.05
+    hi[:, 5] += 50.0
+    m["nasa_high"] = hi
+    return m
+
+
+# c4: the 111-species shape runs the kernels whose species table is read from
+# global memory, with the switch temperatures staged in LDS
+@pytest.mark.parametrize("cfg,G", [("c2", 16), ("c4", 0)])
+def test_rhs_parity_at_range_switch(R, cfg, G):
+    _say("rhs at T_mid", cfg, "G", G)
+    m = _range_switch_mech(cfg)
+    gm, om = R.Mechanism(m), O.Model(m)
+    st = synth.config_states(cfg, 8)
+    Tm = np.unique(np.asarray(m["T_mid"], dtype=np.float64))
+    T = np.concatenate([Tm, np.nextafter(Tm, 0.0)])      # at and one ulp below
+    idx = np.arange(len(T)) % len(st["T"])
+    P = np.ascontiguousarray(st["P"][idx])
+    Y = np.ascontiguousarray(st["Y"][idx])
+    fg = R.rhs(gm, T, P, Y, lanes_per_cell=G)
+    fo = om.rhs(T, P, Y)
+    scale = np.abs(fo[:, 1:]).max(axis=1, keepdims=True)
+    eY = np.abs(fg[:, 1:] - fo[:, 1:]) / scale
+    eT = np.abs(fg[:, 0] - fo[:, 0]) / np.abs(fo[:, 0])
+    _say("max eY", eY.max(), "max eT", eT.max())
+    assert eY.max() <= 1e-12
+    assert eT.max() <= 1e-11
+
+
 max_flips = PT.max_flips
 
 
